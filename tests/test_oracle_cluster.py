@@ -1,0 +1,328 @@
+"""Pins of the oracle's three-threshold clustering (paper §2, Parallelization).
+
+The paper prints no worked example, so the oracle is pinned by:
+* hand-built channels whose clusters were worked out by hand (tests/golden/hand_channels.json);
+* closed forms of the flags at exact ties;
+* a brute-force interval enumeration on tiny windows (different algorithm, exact rationals);
+* the paper's own parallel formulation (seed array -> per-seed boundary search -> dedupe);
+* invariants on generated full-size events.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import fedgen
+import oracle
+from helpers import (NS, calib_arrays, event_from_runs, golden_calib, golden_event,
+                     parse_channel_set, round_f32, fmaf_exact)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_channels.json")
+CASES = json.load(open(GOLDEN))["cases"]
+
+
+def _expected(case):
+    exp = np.zeros(len(case["clusters"]), dtype=oracle.CLUSTER_DTYPE)
+    for i, (ch, first, width, charge, bary) in enumerate(case["clusters"]):
+        exp[i] = (ch, first, width, charge, round_f32(Fraction(bary)))
+    return exp
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c["name"] for c in CASES])
+def test_hand_built_channels(case):
+    zs, fo, n_fed = golden_event(case)
+    noise, gain, bad = golden_calib(case, n_fed)
+    out = oracle.process_event(zs, fo, noise, gain, bad)
+    exp = _expected(case)
+    assert out.cl.size == exp.size, (out.cl, exp)
+    for f in ("channel", "first", "width", "charge"):
+        np.testing.assert_array_equal(out.cl[f], exp[f])
+    # the barycenter is the exact quotient rounded once to binary64 and then to binary32; the
+    # bound below is the benchmark spec's tolerance, the equality is this project's reading
+    for got, (_, _, _, _, b) in zip(out.cl["barycenter"], case["clusters"]):
+        assert abs(Fraction(float(got)) - Fraction(b)) <= Fraction(b) * Fraction(1, 10**6) + 0
+        assert got == np.float32(float(Fraction(b)))
+    np.testing.assert_array_equal(out.adc, np.array(case["adcs"], dtype=np.uint16))
+    bad_ch = parse_channel_set(case.get("malformed", []))
+    assert sorted(np.flatnonzero(out.chan_status & 1).tolist()) == bad_ch
+
+
+def _flags_for(noise_val, adcs):
+    noise, gain, bad = calib_arrays(1, noise=noise_val)
+    adc = np.zeros(96 * NS, dtype=np.uint8)
+    adc[:len(adcs)] = adcs
+    return oracle.flags(adc, noise, gain, bad)[:len(adcs)]
+
+
+def test_flags_closed_form_unit_noise():
+    # n = 1: active <=> a > 2 <=> a >= 3 ; seed <=> a > 3 <=> a >= 4
+    a = np.arange(256)
+    fl = _flags_for(1.0, a)
+    np.testing.assert_array_equal(fl & 1, (a >= 3).astype(np.uint8))
+    np.testing.assert_array_equal(fl >> 1, (a >= 4).astype(np.uint8))
+
+
+def test_flags_exact_ties():
+    a = np.arange(256)
+    fl = _flags_for(1.5, a)            # 2n = 3.0 and 3n = 4.5 exactly
+    np.testing.assert_array_equal(fl & 1, (a >= 4).astype(np.uint8))
+    np.testing.assert_array_equal(fl >> 1, (a >= 5).astype(np.uint8))
+    fl = _flags_for(2.0, a)            # 3n = 6: a = 6 is active but not a seed
+    np.testing.assert_array_equal(fl & 1, (a >= 5).astype(np.uint8))
+    np.testing.assert_array_equal(fl >> 1, (a >= 7).astype(np.uint8))
+    fl = _flags_for(0.0, a)            # zero noise: any nonzero ADC is a seed
+    np.testing.assert_array_equal(fl, np.where(a > 0, 3, 0).astype(np.uint8))
+
+
+def test_flags_product_is_rounded_to_float32():
+    # n = 1.3f: T*n in FP32 is 2.6f (rounded) -> a >= 3 active; both sides agree on integers
+    rng = np.random.default_rng(5)
+    for n in rng.uniform(0.1, 100.0, size=200).astype(np.float32):
+        a = np.arange(256)
+        fl = _flags_for(float(n), a)
+        t_ch = np.float32(2.0) * n
+        t_sd = np.float32(3.0) * n
+        np.testing.assert_array_equal(fl & 1, (a > t_ch).astype(np.uint8))
+        np.testing.assert_array_equal(fl >> 1, ((a > t_ch) & (a > t_sd)).astype(np.uint8))
+
+
+def test_cluster_threshold_exact_square_roots():
+    # width 4, n = 2: S = 16, threshold 5*4 = 20; seeds need a > 6 and actives a > 4
+    noise, gain, bad = calib_arrays(1, noise=2.0)
+    runs = {0: [(10, [7, 5, 4 + 1, 3 + 0])]}      # strip 13 a=3 is inactive -> width 3
+    zs, fo = event_from_runs(runs)
+    out = oracle.process_event(zs, fo, noise, gain, bad)
+    # width 3: S = 12, 5*sqrtf(12) = 17.32..., Q = 17 -> rejected
+    assert out.cl.size == 0
+    runs = {0: [(10, [7, 5, 5, 5])]}               # width 4, Q = 22 >= 20
+    zs, fo = event_from_runs(runs)
+    assert oracle.process_event(zs, fo, noise, gain, bad).cl.size == 1
+    # n = 1, width 9: S = 9, threshold 15; all actives are >= 3 so any seeded 9-run passes
+    noise1, _, _ = calib_arrays(1, noise=1.0)
+    zs, fo = event_from_runs({0: [(0, [4] + [3] * 8)]})
+    out = oracle.process_event(zs, fo, noise1, gain, bad)
+    assert out.cl.size == 1 and out.cl["width"][0] == 9
+
+
+def test_gain_rounding_ties_to_even():
+    noise, gain, bad = calib_arrays(1)
+    gain[0] = 2.0
+    runs = {0: [(10, [5]), (20, [7]), (30, [9]), (40, [11])]}
+    zs, fo = event_from_runs(runs)
+    out = oracle.process_event(zs, fo, noise, gain, bad)
+    # 2.5 -> 2, 3.5 -> 4, 4.5 -> 4, 5.5 -> 6
+    np.testing.assert_array_equal(out.adc, [2, 4, 4, 6])
+    gain[0] = 1.0
+    out = oracle.process_event(zs, fo, noise, gain, bad)
+    np.testing.assert_array_equal(out.adc, [5, 7, 9, 11])
+
+
+def test_barycenter_closed_forms():
+    noise, gain, bad = calib_arrays(1)
+    runs = {0: [(100, [10, 30])], 1: [(7, [9, 9, 9])], 2: [(0, [12])]}
+    zs, fo = event_from_runs(runs)
+    out = oracle.process_event(zs, fo, noise, gain, bad)
+    b = out.cl["barycenter"]
+    assert b[0] == np.float32(100.5 + 30 / 40)     # l + 0.5 + c2 / (c1 + c2)
+    assert b[1] == np.float32(8.5)                 # symmetric -> centre
+    assert b[2] == np.float32(0.5)                 # single strip -> s + 0.5
+
+
+def test_capacity_overflow_counts_everything():
+    noise, gain, bad = calib_arrays(1)
+    runs = {0: [(2 * k, [5]) for k in range(20)]}
+    zs, fo = event_from_runs(runs)
+    adc, _, _ = oracle.unpack(zs, fo)
+    out = oracle.cluster(adc, noise, gain, bad, cap_cl=5, cap_adc=3)
+    assert out.status == -2
+    full = oracle.cluster(adc, noise, gain, bad)
+    assert full.cl.size == 20
+    np.testing.assert_array_equal(out.cl, full.cl[:5])
+    np.testing.assert_array_equal(out.adc, full.adc[:3])
+
+
+# ---- brute force on tiny windows -----------------------------------------------------------
+
+def _brute_force_channel(a, n, g, bad, t_seed=3.0, t_ch=2.0, t_cl=5.0):
+    """Enumerate every interval [l, r] of one channel and keep those that satisfy the cluster
+    definition. Exact rationals stand in for FP32 where a rounding decides the result."""
+    T_ch, T_sd, T_cl = np.float32(t_ch), np.float32(t_seed), np.float32(t_cl)
+
+    def usable(s):
+        gs = g[s // 128]
+        return (bad[s] == 0 and not np.isnan(n[s]) and n[s] >= 0 and not np.isinf(n[s])
+                and not np.isnan(gs) and gs > 0)
+
+    act = [usable(s) and Fraction(int(a[s])) > Fraction(float(T_ch * n[s])) for s in range(NS)]
+    sd = [act[s] and Fraction(int(a[s])) > Fraction(float(T_sd * n[s])) for s in range(NS)]
+    out = []
+    for l in range(NS):
+        if not act[l] or (l > 0 and act[l - 1]):
+            continue
+        for r in range(l, NS):
+            if not all(act[l:r + 1]):
+                break
+            if r + 1 < NS and act[r + 1]:
+                continue
+            if not any(sd[l:r + 1]):
+                continue
+            q = sum(int(x) for x in a[l:r + 1])
+            S = np.float32(0)
+            for s in range(l, r + 1):
+                S = fmaf_exact(n[s], n[s], S)
+            root = np.float32(np.sqrt(np.float64(S)))        # double then single: innocuous
+            if not Fraction(q) >= Fraction(float(T_cl * root)):
+                continue
+            cs = []
+            for s in range(l, r + 1):
+                qq = round_f32(Fraction(int(a[s])) / Fraction(float(g[s // 128])))
+                v = Fraction(float(qq))
+                fl = int(v)                                    # rint, ties to even
+                frac = v - fl
+                rv = fl + (1 if frac > Fraction(1, 2) or (frac == Fraction(1, 2) and fl % 2) else 0)
+                cs.append(min(rv, 65535))
+            tot = sum(cs)
+            bary = (Fraction(sum((2 * s + 1) * c for s, c in zip(range(l, r + 1), cs)), 2 * tot)
+                    if tot else Fraction(l) + Fraction(r - l + 1, 2))
+            out.append((l, r - l + 1, tot, bary, cs))
+    return out
+
+
+@pytest.mark.parametrize("window", [0, 61, 125, 189, 250])
+def test_brute_force_windows(window):
+    """6-strip windows at the channel start, across strips 63|64 and 127|128 (APV edge), across
+    191|192 and at the channel end. ADC alphabet around each strip's thresholds, random bad
+    flags, one random assignment per channel, 4 FEDs per call."""
+    rng = np.random.default_rng(1000 + window)
+    n_fed = 4
+    noise, gain, bad = calib_arrays(n_fed)
+    noise[:] = rng.choice(np.array([0.75, 1.0, 1.5, 2.0, 3.0, 4.0, 1.3, 2.7], np.float32),
+                          size=noise.size)
+    gain[:] = rng.choice(np.array([1.0, 2.0, 0.5, 1.1, 0.9], np.float32), size=gain.size)
+    dense = np.zeros(n_fed * 96 * NS, dtype=np.uint8)
+    for c in range(n_fed * 96):
+        for s in range(window, window + 6):
+            i = c * NS + s
+            n = noise[i]
+            choices = [0, int(2 * n), int(2 * n) + 1, int(3 * n), int(3 * n) + 1, 255]
+            dense[i] = choices[rng.integers(len(choices))]
+            bad[i] = rng.random() < 0.15
+    zs, fo = fedgen.encode_dense(dense.reshape(-1, NS), dense.reshape(-1, NS) > 0)
+    out = oracle.process_event(zs, fo, noise, gain, bad)
+    got = {}
+    k = 0
+    for rec in out.cl:
+        got.setdefault(int(rec["channel"]), []).append(
+            (int(rec["first"]), int(rec["width"]), int(rec["charge"]), float(rec["barycenter"]),
+             out.adc[k:k + int(rec["width"])].tolist()))
+        k += int(rec["width"])
+    for c in range(n_fed * 96):
+        sl = slice(c * NS, (c + 1) * NS)
+        want = _brute_force_channel(dense[sl], noise[sl], gain[2 * c:2 * c + 2], bad[sl])
+        have = got.get(c, [])
+        assert len(have) == len(want), (c, have, want)
+        for (l, w, q, b, cs), (l2, w2, q2, b2, cs2) in zip(have, want):
+            assert (l, w, q, cs) == (l2, w2, q2, cs2)
+            assert np.float32(b) == np.float32(float(b2))
+
+
+# ---- the paper's parallel formulation ------------------------------------------------------
+
+def _per_seed_formulation(adc, noise, gain, bad, t_seed=3.0, t_ch=2.0, t_cl=5.0):
+    """Paper §2: build the array of seed-strip indices (seed seeking over all strips), form a
+    cluster around each seed by searching left and right boundaries, then check the cluster
+    threshold. Seeds of one run yield the same boundaries; one cluster per distinct boundary
+    pair. Vectorised NumPy, written independently of the oracle's sequential scan."""
+    T_ch, T_sd, T_cl = np.float32(t_ch), np.float32(t_seed), np.float32(t_cl)
+    a = adc.astype(np.float32)
+    g = np.repeat(gain, 128)
+    usable = (bad == 0) & ~np.isnan(noise) & (noise >= 0) & ~np.isinf(noise) & ~np.isnan(g) & (g > 0)
+    act = usable & (a > T_ch * noise)
+    seed = act & (a > T_sd * noise)
+    strip = np.arange(adc.size) % NS
+    seeds = np.flatnonzero(seed)
+    # boundary search: run starts/ends of the active mask, channel edges break runs
+    is_start = act & ((strip == 0) | ~np.roll(act, 1))
+    is_end = act & ((strip == NS - 1) | ~np.roll(act, -1))
+    starts = np.flatnonzero(is_start)
+    ends = np.flatnonzero(is_end)
+    left = starts[np.searchsorted(starts, seeds, side="right") - 1]
+    right = ends[np.searchsorted(ends, seeds, side="left")]
+    pairs = np.unique(np.stack([left, right], axis=1), axis=0)
+    res = []
+    for l, r in pairs:
+        q = int(adc[l:r + 1].astype(np.int64).sum())
+        # S: left-to-right fmaf; n*n and the running sum are exact in the x87 64-bit mantissa
+        # for the noise ranges used here, so one rounding to binary32 per step remains
+        S = np.float32(0)
+        for s in range(l, r + 1):
+            S = np.float32(np.longdouble(noise[s]) * np.longdouble(noise[s]) + np.longdouble(S))
+        if not np.float32(q) >= T_cl * np.sqrt(S, dtype=np.float32):
+            continue
+        c = np.minimum(np.rint(a[l:r + 1] / g[l:r + 1]), 65535).astype(np.int64)
+        tot = int(c.sum())
+        pos = np.arange(l, r + 1) % NS
+        bary = (np.float32(float(Fraction(int(((2 * pos + 1) * c).sum()), 2 * tot)))
+                if tot else np.float32(l % NS + (r - l + 1) / 2))
+        res.append((l // NS, l % NS, r - l + 1, tot, bary, c))
+    return res
+
+
+@pytest.mark.parametrize("cfg_id,index", [(0, 0), (0, 1), (4, 0)])
+def test_per_seed_formulation_matches(cfg_id, index):
+    cfg = fedgen.CONFIGS[cfg_id]
+    if cfg_id == 4:
+        cfg = cfg.with_(n_fed=40)          # the stress distribution on a 40-FED slice
+    assert cfg.noise_lo >= 2.0 and cfg.noise_hi <= 16.0   # keeps the longdouble sum exact
+    cal = fedgen.make_calibration(cfg)
+    ev = fedgen.make_event(cfg, cal, index)
+    out = oracle.process_event(ev.zs, ev.fed_offset, cal.noise, cal.gain, cal.bad)
+    ref = _per_seed_formulation(ev.dense, cal.noise, cal.gain, cal.bad)
+    assert out.cl.size == len(ref)
+    np.testing.assert_array_equal(out.cl["channel"], [r[0] for r in ref])
+    np.testing.assert_array_equal(out.cl["first"], [r[1] for r in ref])
+    np.testing.assert_array_equal(out.cl["width"], [r[2] for r in ref])
+    np.testing.assert_array_equal(out.cl["charge"], [r[3] for r in ref])
+    np.testing.assert_array_equal(out.cl["barycenter"], np.array([r[4] for r in ref], np.float32))
+    np.testing.assert_array_equal(out.adc, np.concatenate([r[5] for r in ref]))
+
+
+# ---- invariants on generated events --------------------------------------------------------
+
+@pytest.mark.parametrize("cfg_id", [0, 1])
+def test_invariants_generated(cfg_id):
+    cfg = fedgen.CONFIGS[cfg_id]
+    cal = fedgen.make_calibration(cfg)
+    ev = fedgen.make_event(cfg, cal, 3)
+    out = oracle.process_event(ev.zs, ev.fed_offset, cal.noise, cal.gain, cal.bad)
+    fl = oracle.flags(ev.dense, cal.noise, cal.gain, cal.bad)
+    act = (fl & 1).astype(bool)
+    seed = (fl & 2).astype(bool)
+    cl = out.cl
+    gidx = cl["channel"].astype(np.int64) * NS + cl["first"]
+    # sorted, disjoint
+    key = cl["channel"].astype(np.int64) * 1024 + cl["first"]
+    assert np.all(np.diff(key) > 0)
+    ends = gidx + cl["width"]
+    assert np.all(gidx[1:] >= ends[:-1])
+    total_w = 0
+    for g0, w in zip(gidx, cl["width"]):
+        w = int(w)
+        assert act[g0:g0 + w].all()                       # every member active (so not bad)
+        assert seed[g0:g0 + w].any()                      # at least one seed
+        s0 = g0 % NS
+        if s0 > 0:
+            assert not act[g0 - 1]                         # maximal on the left
+        if s0 + w < NS:
+            assert not act[g0 + w]                         # maximal on the right
+        q = int(ev.dense[g0:g0 + w].astype(np.int64).sum())
+        nn = cal.noise[g0:g0 + w].astype(np.float64)
+        assert q >= 5.0 * np.sqrt((nn * nn).sum()) * (1 - 1e-6)
+        total_w += w
+    assert total_w <= act.sum()
+    assert out.adc.size == total_w
+    # magnitudes of the same order as the paper's per-event counts (800k strips, 150k seeds)
+    if cfg_id == 1:
+        assert 2e5 < ev.n_digis < 2e6 and 5e4 < seed.sum() < 1e6
