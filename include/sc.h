@@ -1,0 +1,210 @@
+/*
+ * sc.h -- C ABI of the MI355X strip-cluster library (libsc.so).
+ *
+ * The library turns zero-suppressed (ZS) raw data of a silicon-strip tracker into clusters, for
+ * the whole detector at once, on one AMD Instinct MI355X (gfx950):
+ *   unpack (ZS records -> per-strip ADCs) -> per-strip calibration (noise, per-APV gain, bad
+ *   strips) -> three-threshold clustering -> clusters with strip range, gain-corrected ADCs,
+ *   charge and barycenter.
+ * Paper: "Parallelizing the Unpacking and Clustering of Detector Data for Reconstruction of
+ * Charged Particle Tracks on Multi-core CPUs and Many-core GPUs" (CTD 2020), §2 Parallelization
+ * (data organisation, unpacking, clustering) and §3 Optimization (multi-event concurrency,
+ * overlap of transfers with compute, cached device allocation).
+ *
+ * Conventions shared by every call
+ *  - Detector: a FED reads 96 channels of 256 strips (§2); an APV serves 128 strips, so channel
+ *    c holds APVs 2c and 2c+1. Global channel index c = fed*96 + ch; strip (c, s) is element
+ *    c*256 + s of every per-strip array.
+ *  - ZS byte format (§2 says only "a variant of CSR, channel = row, strip = column"; this is the
+ *    concrete reading): FED f of an event is zs[fed_offset[f] .. fed_offset[f+1]), its 96 channel
+ *    records back to back. A record is a little-endian u16 P (payload bytes that follow) and P
+ *    bytes of runs (u8 first strip, u8 count, count x u8 ADC) in increasing strip order; adjacent
+ *    runs are legal (runs longer than 255 strips are written that way).
+ *  - Malformed input is data, not an error: a channel whose record breaks the format reads as
+ *    all-zero ADCs and is flagged (SC_CH_MALFORMED); a record that overruns its FED flags that
+ *    channel and every later channel of the FED; bytes after the 96th record only set
+ *    SC_CH_FED_TRAILING. Calls then return SC_MALFORMED (positive: outputs are valid).
+ *  - Clustering (§2, "three thresholds"): a strip is active when it is usable and
+ *    ADC > t_channel*noise, a seed when also ADC > t_seed*noise (FP32 products, strict
+ *    compares); a candidate is a maximal run of active strips inside one channel holding at least
+ *    one seed; it is accepted when (float)sum(ADC) >= t_cluster*sqrtf(S), S accumulated as
+ *    S = fmaf(n, n, S) from the left strip to the right one. A strip is unusable when its bad
+ *    flag is set, its noise is NaN, negative or infinite, or its APV gain is NaN or <= 0.
+ *  - Outputs per accepted cluster: channel, first strip, width, member ADCs
+ *    c = min(rintf(ADC/gain), 65535) (u16, ties to even), charge = sum c and
+ *    barycenter = sum((s+0.5)*c)/sum(c) (double quotient rounded to float; first+width/2 when the
+ *    charge is 0), channel-local strip units. Clusters come in ascending (channel, first) order;
+ *    member ADCs follow cluster after cluster (offsets = prefix sums of width).
+ *  - Memory: every pointer argument of a call lies in the memory kind the call names (sc_mem):
+ *    host memory, or device memory of the context's GPU. The caller owns every buffer it passes;
+ *    the context owns its resident calibration, workspaces, graphs and pinned staging.
+ *  - Errors: no exception crosses the ABI. Negative returns are failures; sc_last_error() then
+ *    describes the last failure of the context. SC_ERR_DEVICE poisons the context: every later
+ *    call returns SC_ERR_DEVICE. Device ZS buffers are read in aligned 16-byte pieces, so bytes up
+ *    to the next 16-byte boundary around a FED may be read (never written); they must lie in
+ *    mapped memory, which every allocation of the HIP runtime satisfies.
+ *  - Threading: synchronous calls (sc_unpack, sc_cluster, sc_process_events) of one context must
+ *    not overlap. sc_submit and sc_poll may be called from any threads, concurrently with each
+ *    other but not with the synchronous calls.
+ */
+#ifndef SC_H
+#define SC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { SC_CHANNELS_PER_FED = 96, SC_STRIPS_PER_CHANNEL = 256, SC_STRIPS_PER_APV = 128 };
+
+/* chan_status bits */
+enum { SC_CH_MALFORMED = 1, SC_CH_FED_TRAILING = 2 };
+
+typedef enum {
+    SC_OK = 0,
+    SC_MALFORMED = 1,          /* done; at least one channel was malformed (zeroed, flagged) */
+    SC_PENDING = 2,            /* sc_poll: not finished yet */
+    SC_ERR_INVALID_ARG = -1,   /* bad argument; nothing was done */
+    SC_ERR_OVERFLOW = -2,      /* an output capacity was too small; n_cl/n_adc hold the needs */
+    SC_ERR_BUDGET = -3,        /* sc_submit: the event can never fit the HBM budget */
+    SC_ERR_AGAIN = -4,         /* sc_submit: admission queue full, try again later */
+    SC_ERR_DEVICE = -5,        /* HIP runtime or kernel failure; the context is unusable */
+    SC_ERR_NOMEM = -6,         /* device or pinned allocation failed */
+    SC_ERR_UNKNOWN_TICKET = -7 /* sc_poll: ticket never issued or already collected */
+} sc_status;
+
+typedef enum { SC_MEM_HOST = 0, SC_MEM_DEVICE = 1 } sc_mem;
+
+typedef struct sc_ctx sc_ctx;
+
+/* Calibration (§2: gain and noise per strip, unpacked per FED channel). Host pointers, copied to
+ * the device by sc_create and kept resident. noise: FP32 ADC counts per strip [n_fed*96*256];
+ * gain: FP32 per APV [n_fed*96*2]; bad: per strip, nonzero = bad [n_fed*96*256].
+ * Thresholds (in units of strip noise) must be finite and >= 0. */
+typedef struct {
+    uint32_t n_fed;
+    const float *noise;
+    const float *gain;
+    const uint8_t *bad;
+    float t_seed;      /* e.g. 3.0 */
+    float t_channel;   /* e.g. 2.0 */
+    float t_cluster;   /* e.g. 5.0 */
+} sc_calib;
+
+/* Context options; fill with sc_default_options() first. */
+typedef struct {
+    int device;            /* HIP device ordinal */
+    void *stream;          /* hipStream_t of the synchronous calls; NULL: a stream of the context */
+    size_t hbm_budget;     /* bytes the server may hold for events in flight; 0: 1/4 of free HBM */
+    uint32_t max_batch;    /* most events per fused launch in the server (default 64) */
+    uint32_t n_streams;    /* server streams, i.e. batches in flight (default 2) */
+    uint32_t queue_depth;  /* server admission queue (default 4096) */
+    const char *tune_cache;/* autotuner cache file (JSON); NULL: none */
+} sc_options;
+
+/* One event: its FED buffers and FED offsets (u64 [n_fed+1], fed_offset[0] is usually 0). */
+typedef struct {
+    const uint8_t *zs;
+    const uint64_t *fed_offset;
+    sc_mem mem;
+} sc_event;
+
+/* One cluster, 16 bytes. */
+typedef struct {
+    uint32_t channel;   /* fed*96 + ch */
+    uint16_t first;     /* first strip, 0..255 */
+    uint16_t width;     /* strips, 1..256 */
+    uint32_t charge;    /* sum of gain-corrected member ADCs */
+    float barycenter;   /* channel-local; strip s spans [s, s+1) */
+} sc_cluster_rec;
+
+/* Cluster output of one event. cl/adc/chan_status lie in memory kind mem; n_cl/n_adc are host
+ * fields written by the library: the produced counts, or the needed counts on SC_ERR_OVERFLOW
+ * (then the first cap_cl clusters / cap_adc ADCs are written and valid). chan_status is optional
+ * (NULL, or n_fed*96 bytes of SC_CH_* bits). A safe capacity for any event is
+ * n_cl <= n_digis and n_adc <= n_digis, where n_digis <= total ZS bytes of the event. */
+typedef struct {
+    sc_cluster_rec *cl;
+    uint32_t cap_cl;
+    uint32_t n_cl;
+    uint16_t *adc;
+    uint32_t cap_adc;
+    uint32_t n_adc;
+    uint8_t *chan_status;
+    sc_mem mem;
+} sc_clusters;
+
+/* Performance-relevant choices of the fused kernel (found by sc_autotune). */
+typedef struct {
+    uint32_t chunk_digis;    /* digis one wave holds in LDS per pass: 768,1024,1536,2048,3072 */
+    uint32_t waves_per_cu;   /* resident waves of the persistent grid per compute unit, 1..32 */
+    uint32_t fed_major;      /* 1: tiles ordered FED-major (calibration reuse), 0: event-major */
+    uint32_t use_graph;      /* 1: replay the batched launch as a captured hipGraph */
+} sc_tuning;
+
+/* Counters of a context. */
+typedef struct {
+    uint64_t launches, events, graph_replays, graph_captures;
+    uint64_t server_batches, server_events, server_rejected_again;
+    double last_kernel_ms;   /* device time of the last fused/cluster launch (HIP events) */
+} sc_stats;
+
+void sc_default_options(sc_options *opt);
+
+/* Create a context on opt->device: validates and uploads the calibration, derives the per-strip
+ * integer thresholds, allocates workspaces. *out is NULL on failure. */
+sc_status sc_create(const sc_calib *calib, const sc_options *opt, sc_ctx **out);
+
+/* Destroy a context: stops the server (pending tickets are dropped), frees everything. */
+void sc_destroy(sc_ctx *ctx);
+
+/* §2 unpacking step alone: ZS event -> dense ADCs (u8 [n_fed*96*256], 0 where no ADC was
+ * recorded) and optional chan_status (u8 [n_fed*96]); outputs in memory kind out_mem.
+ * Returns SC_OK or SC_MALFORMED when done. */
+sc_status sc_unpack(sc_ctx *ctx, const sc_event *ev, uint8_t *adc_dense, uint8_t *chan_status,
+                    sc_mem out_mem);
+
+/* §2 clustering step alone, from dense ADCs (u8 [n_fed*96*256] in memory kind in_mem).
+ * out->chan_status is ignored. sc_unpack + sc_cluster is the plain per-event GPU path.
+ * Returns SC_OK, or SC_ERR_OVERFLOW with the needed sizes in out. */
+sc_status sc_cluster(sc_ctx *ctx, const uint8_t *adc_dense, sc_mem in_mem, sc_clusters *out);
+
+/* Unpack and cluster n events in one fused, persistent launch (§3 multi-event concurrency).
+ * Events may differ in size and memory kind; out[i] receives event i's clusters and ev_status[i]
+ * (optional) its own status (SC_OK, SC_MALFORMED or SC_ERR_OVERFLOW). Returns SC_ERR_OVERFLOW if
+ * any event overflowed, else SC_MALFORMED if any was malformed, else SC_OK. Results of an event
+ * do not depend on the other events of the batch. */
+sc_status sc_process_events(sc_ctx *ctx, const sc_event *ev, uint32_t n, sc_clusters *out,
+                            sc_status *ev_status);
+
+/* Serving. sc_submit admits one event into the server's queue (starting the server thread on
+ * first use) and returns a ticket. Host ZS bytes are copied before the call returns; device ZS
+ * buffers and every output buffer must stay valid until sc_poll returns a final status. Events
+ * that arrive while others run join the next batch as soon as a stream slot and HBM budget are
+ * free (continuous batching). Returns SC_OK, SC_ERR_AGAIN (queue full), SC_ERR_BUDGET (can never
+ * fit) or SC_ERR_INVALID_ARG. */
+sc_status sc_submit(sc_ctx *ctx, const sc_event *ev, sc_clusters *out, uint64_t *ticket);
+
+/* Wait up to timeout_us (0: do not wait, <0: forever) for a ticket. Returns SC_PENDING if not
+ * finished, else the event's final status (as for sc_process_events), after which the ticket is
+ * forgotten. */
+sc_status sc_poll(sc_ctx *ctx, uint64_t ticket, int64_t timeout_us);
+
+/* Tuning of the fused kernel. sc_autotune times every candidate choice on the given events
+ * (device or host), checks that all choices give identical clusters, keeps the fastest and, if
+ * opt->tune_cache was set, stores it there. */
+sc_status sc_get_tuning(const sc_ctx *ctx, sc_tuning *t);
+sc_status sc_set_tuning(sc_ctx *ctx, const sc_tuning *t);
+sc_status sc_autotune(sc_ctx *ctx, const sc_event *ev, uint32_t n, sc_tuning *best);
+
+sc_status sc_get_stats(const sc_ctx *ctx, sc_stats *s);
+
+/* Text of the last failure of this context (or of the last failed sc_create when ctx is NULL). */
+const char *sc_last_error(const sc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SC_H */

@@ -1,0 +1,51 @@
+"""Compile libsc.so (HIP kernels for gfx950 + C++ host runtime) in the package directory."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libsc.so")
+INCLUDE = os.path.join(ROOT, "include")
+ARCH = os.environ.get("SC_OFFLOAD_ARCH", "gfx950")
+
+# Device code: no FP contraction (the one fused step is an explicit fmaf), correctly rounded FP32
+# division and square root, and no packed-FP32 instructions.
+DEVICE_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
+                "-fhip-fp32-correctly-rounded-divide-sqrt", "-Xclang", "-target-feature",
+                "-Xclang", "-packed-fp32-ops", "-Wall", "-I", INCLUDE, "-I", CSRC]
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-x", "c++", "-D__HIP_PLATFORM_AMD__",
+              "-I", os.path.join(ROCM, "include"), "-I", INCLUDE, "-I", CSRC]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        sys.stderr.write(err + "\n")
+        raise RuntimeError(f"build step failed: {' '.join(cmd)}")
+    return err
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    k_obj = os.path.join(BUILD, "sc_kernels.o")
+    r_obj = os.path.join(BUILD, "sc_runtime.o")
+    _run(["hipcc", *DEVICE_FLAGS, "-c", os.path.join(CSRC, "sc_kernels.hip"), "-o", k_obj])
+    _run(["hipcc", *HOST_FLAGS, "-c", os.path.join(CSRC, "sc_runtime.cpp"), "-o", r_obj])
+    tmp = LIB + ".tmp"
+    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, k_obj, r_obj,
+          "-lpthread"])
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB}")
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

@@ -1,0 +1,70 @@
+// sc_internal.h -- types shared by the HIP kernels and the host runtime of libsc.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sc.h"
+
+namespace sc {
+
+constexpr int kChannelsPerFed = 96;
+constexpr int kStripsPerChannel = 256;
+constexpr int kStripsPerApv = 128;
+constexpr int kWave = 64;
+
+// One event of a fused launch, in device memory.
+struct EventDesc {
+    const uint8_t* zs;          // FED buffers of the event
+    const uint64_t* fed_off;    // [n_fed + 1]
+    sc_cluster_rec* cl;          // output clusters
+    uint16_t* adc;              // output member ADCs
+    uint8_t* chan_status;       // optional [n_fed * 96]
+    uint32_t cap_cl;
+    uint32_t cap_adc;
+};
+
+// Per-event result written by the last FED tile of the event (counts) and by any tile (flags).
+enum : uint32_t { kResMalformed = 1u, kResTrailing = 2u, kResSpinTimeout = 4u };
+struct EventResult {
+    uint32_t n_cl;
+    uint32_t n_adc;
+    uint32_t flags;
+    uint32_t pad;
+};
+
+// Device-resident calibration, derived once per context.
+struct DeviceCalib {
+    const uint2* strip;   // per strip: {noise FP32 bits, k_channel | k_seed << 8}
+    const float* gain;    // per APV
+    uint32_t n_fed;
+    float t_cluster;
+};
+
+struct FusedArgs {
+    const EventDesc* ev;
+    EventResult* res;
+    unsigned long long* tile_state;  // [n_ev * n_fed] decoupled look-back words
+    uint32_t* queue;                 // tile ticket counter
+    DeviceCalib cal;
+    uint32_t n_ev;
+    uint32_t fed_major;
+};
+
+// Launch helpers (sc_kernels.hip). All enqueue on `stream` and return the launch error.
+hipError_t launch_derive_calib(const float* noise, const float* gain, const uint8_t* bad,
+                               uint32_t n_fed, float t_seed, float t_channel, uint2* strip_out,
+                               hipStream_t stream);
+hipError_t launch_reset(const FusedArgs& a, uint32_t n_fed, hipStream_t stream);
+hipError_t launch_fused(const FusedArgs& a, uint32_t chunk_digis, uint32_t grid,
+                        hipStream_t stream);
+hipError_t launch_cluster_dense(const uint8_t* adc_dense, const FusedArgs& a,
+                                uint32_t chunk_digis, uint32_t grid, hipStream_t stream);
+hipError_t launch_unpack(const uint8_t* zs, const uint64_t* fed_off, uint32_t n_fed,
+                         uint8_t* adc_dense, uint8_t* chan_status, EventResult* res,
+                         hipStream_t stream);
+// Resident workgroups per compute unit for the fused kernel with this chunk size.
+int fused_blocks_per_cu(uint32_t chunk_digis, bool dense);
+bool chunk_digis_supported(uint32_t chunk_digis);
+
+}  // namespace sc

@@ -1,0 +1,1065 @@
+// sc_runtime.cpp -- host runtime of libsc.so: context, resident calibration, workspaces,
+// synchronous calls, hipGraph replay of batched launches, the serving loop and the autotuner.
+//
+// Paper §3 (Optimization) runs several events concurrently (one CUDA stream per event driven by
+// OpenMP threads) and relies on a caching device allocator. Here events of a batch share one
+// persistent fused launch, workspaces are allocated once per context and only grow, and the
+// server overlaps batches on a small set of HIP streams.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "sc.h"
+#include "sc_internal.h"
+
+using namespace sc;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= n) return hipSuccess;
+        if (p) { (void)hipFree(p); p = nullptr; n = 0; }
+        size_t want = align_up(std::max<size_t>(bytes, 256), 4096);
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) n = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct PinBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= n) return hipSuccess;
+        if (p) { (void)hipHostFree(p); p = nullptr; n = 0; }
+        size_t want = align_up(std::max<size_t>(bytes, 256), 4096);
+        hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+        if (e == hipSuccess) n = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Buffers of one batched launch. Grown on demand, never shrunk (a caching arena in the spirit of
+// the paper's cached allocator, without per-event allocation).
+struct Workspace {
+    DevBuf desc, res, state, queue, zs, fo, cl, adc, chst, dense;
+    PinBuf h_desc, h_res, h_zs, h_fo;
+    uint64_t generation = 0;   // bumps whenever a buffer that graphs capture moves
+    hipError_t ensure_batch(uint32_t n_ev, uint32_t n_fed) {
+        void* old[4] = {desc.p, res.p, state.p, queue.p};
+        void* oldh[2] = {h_desc.p, h_res.p};
+        hipError_t e;
+        if ((e = desc.ensure(sizeof(EventDesc) * n_ev)) != hipSuccess) return e;
+        if ((e = res.ensure(sizeof(EventResult) * n_ev)) != hipSuccess) return e;
+        if ((e = state.ensure(sizeof(unsigned long long) * (size_t)n_ev * n_fed)) != hipSuccess) return e;
+        if ((e = queue.ensure(64)) != hipSuccess) return e;
+        if ((e = h_desc.ensure(sizeof(EventDesc) * n_ev)) != hipSuccess) return e;
+        if ((e = h_res.ensure(sizeof(EventResult) * n_ev)) != hipSuccess) return e;
+        if (old[0] != desc.p || old[1] != res.p || old[2] != state.p || old[3] != queue.p ||
+            oldh[0] != h_desc.p || oldh[1] != h_res.p)
+            ++generation;
+        return hipSuccess;
+    }
+    void release() {
+        for (DevBuf* b : {&desc, &res, &state, &queue, &zs, &fo, &cl, &adc, &chst, &dense}) b->release();
+        for (PinBuf* b : {&h_desc, &h_res, &h_zs, &h_fo}) b->release();
+    }
+};
+
+struct GraphKey {
+    uint32_t n_ev, chunk, grid, fed_major;
+    uint64_t gen;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(n_ev, chunk, grid, fed_major, gen) <
+               std::tie(o.n_ev, o.chunk, o.grid, o.fed_major, o.gen);
+    }
+};
+
+struct Req;
+
+}  // namespace
+
+struct Server;
+
+struct sc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint32_t n_fed = 0;
+    float t_seed = 3, t_channel = 2, t_cluster = 5;
+    uint2* d_strip = nullptr;
+    float* d_gain = nullptr;
+    int n_cu = 0;
+    std::string device_name;
+    sc_tuning tuning{};
+    sc_options opt{};
+    std::string tune_cache;
+    std::atomic<bool> poisoned{false};
+    mutable std::mutex err_mu;
+    std::string last_error;
+    Workspace ws;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    sc_stats stats{};
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    std::unique_ptr<Server> server;
+    std::mutex server_mu;
+};
+
+namespace {
+
+sc_status fail(sc_ctx* c, sc_status st, const std::string& msg) {
+    if (c) {
+        std::lock_guard<std::mutex> g(c->err_mu);
+        c->last_error = msg;
+    } else {
+        g_create_error = msg;
+    }
+    return st;
+}
+
+sc_status device_fail(sc_ctx* c, hipError_t e, const char* where) {
+    c->poisoned = true;
+    return fail(c, SC_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define SC_HIP(ctx, call)                                        \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return device_fail(ctx, e_, #call); \
+    } while (0)
+
+uint32_t grid_for(const sc_ctx* c, uint32_t n_tiles, bool dense) {
+    const int occ = std::max(1, fused_blocks_per_cu(c->tuning.chunk_digis, dense));
+    const uint32_t per_cu = std::max<uint32_t>(1, std::min<uint32_t>(c->tuning.waves_per_cu, occ));
+    const uint32_t g = per_cu * (uint32_t)std::max(1, c->n_cu);
+    return std::max<uint32_t>(1, std::min<uint32_t>(g, n_tiles));
+}
+
+// Largest byte offset an event references (its buffer must be at least this long).
+uint64_t event_span(const uint64_t* fo, uint32_t n_fed) {
+    uint64_t m = 0;
+    for (uint32_t f = 0; f <= n_fed; ++f) m = std::max(m, fo[f]);
+    return m;
+}
+
+constexpr uint64_t kMaxEventBytes = 1ull << 31;
+
+// Device time between the two timing events around the last kernel (-1 if unavailable); a failed
+// query must not leave a stale error behind for the next launch check.
+void record_kernel_ms(sc_ctx* c) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) {
+        c->stats.last_kernel_ms = ms;
+    } else {
+        (void)hipGetLastError();
+        c->stats.last_kernel_ms = -1.0;
+    }
+}
+
+sc_status check_event(sc_ctx* c, const sc_event& ev) {
+    if (!ev.zs && ev.mem == SC_MEM_HOST) return fail(c, SC_ERR_INVALID_ARG, "event zs is NULL");
+    if (!ev.fed_offset) return fail(c, SC_ERR_INVALID_ARG, "event fed_offset is NULL");
+    if (ev.mem != SC_MEM_HOST && ev.mem != SC_MEM_DEVICE)
+        return fail(c, SC_ERR_INVALID_ARG, "event mem kind");
+    if (ev.mem == SC_MEM_HOST && event_span(ev.fed_offset, c->n_fed) > kMaxEventBytes)
+        return fail(c, SC_ERR_INVALID_ARG, "event larger than 2 GiB");
+    return SC_OK;
+}
+
+sc_status check_out(sc_ctx* c, const sc_clusters& o) {
+    if (o.mem != SC_MEM_HOST && o.mem != SC_MEM_DEVICE)
+        return fail(c, SC_ERR_INVALID_ARG, "output mem kind");
+    if ((o.cap_cl && !o.cl) || (o.cap_adc && !o.adc))
+        return fail(c, SC_ERR_INVALID_ARG, "output buffer NULL with nonzero capacity");
+    if (o.mem == SC_MEM_DEVICE && (reinterpret_cast<uintptr_t>(o.cl) & 15u))
+        return fail(c, SC_ERR_INVALID_ARG, "device cluster buffer must be 16-byte aligned");
+    return SC_OK;
+}
+
+sc_status status_of(const EventResult& r, const sc_clusters& o) {
+    if (r.n_cl > o.cap_cl || r.n_adc > o.cap_adc) return SC_ERR_OVERFLOW;
+    if (r.flags & kResMalformed) return SC_MALFORMED;
+    return SC_OK;
+}
+
+sc_status worst(sc_status a, sc_status b) {
+    auto rank = [](sc_status s) {
+        switch (s) {
+            case SC_OK: return 0;
+            case SC_MALFORMED: return 1;
+            case SC_ERR_OVERFLOW: return 2;
+            default: return 3;
+        }
+    };
+    return rank(b) > rank(a) ? b : a;
+}
+
+// ---- batch staging: fills ws descriptors (host mirror), copies host inputs ----------------
+struct Staged {
+    std::vector<uint64_t> zs_off;    // per event, offset of its bytes in ws.zs (host events)
+    std::vector<uint64_t> fo_off;    // per event, offset of its fed offsets in ws.fo
+    std::vector<uint64_t> cl_off, adc_off, st_off;   // host-output staging offsets
+};
+
+sc_status stage_batch(sc_ctx* c, Workspace& ws, const sc_event* ev, uint32_t n,
+                      const sc_clusters* out, hipStream_t s, Staged& st) {
+    const uint32_t n_fed = c->n_fed;
+    SC_HIP(c, ws.ensure_batch(n, n_fed));
+    // host inputs -> pinned -> device
+    uint64_t zs_bytes = 0, fo_bytes = 0;
+    st.zs_off.assign(n, 0);
+    st.fo_off.assign(n, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (ev[i].mem == SC_MEM_HOST) {
+            st.zs_off[i] = zs_bytes;
+            zs_bytes += align_up(event_span(ev[i].fed_offset, n_fed), 16);
+            st.fo_off[i] = fo_bytes;
+            fo_bytes += align_up(sizeof(uint64_t) * (n_fed + 1), 16);
+        }
+    }
+    if (zs_bytes) {
+        SC_HIP(c, ws.zs.ensure(zs_bytes));
+        SC_HIP(c, ws.h_zs.ensure(zs_bytes));
+    }
+    if (fo_bytes) {
+        SC_HIP(c, ws.fo.ensure(fo_bytes));
+        SC_HIP(c, ws.h_fo.ensure(fo_bytes));
+    }
+    // host outputs -> device staging
+    uint64_t cl_b = 0, adc_b = 0, st_b = 0;
+    st.cl_off.assign(n, 0);
+    st.adc_off.assign(n, 0);
+    st.st_off.assign(n, 0);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (out[i].mem == SC_MEM_HOST) {
+            st.cl_off[i] = cl_b;
+            cl_b += align_up(sizeof(sc_cluster_rec) * (uint64_t)out[i].cap_cl, 256);
+            st.adc_off[i] = adc_b;
+            adc_b += align_up(sizeof(uint16_t) * (uint64_t)out[i].cap_adc, 256);
+            if (out[i].chan_status) {
+                st.st_off[i] = st_b;
+                st_b += align_up((uint64_t)n_fed * kChannelsPerFed, 256);
+            }
+        }
+    }
+    if (cl_b) SC_HIP(c, ws.cl.ensure(cl_b));
+    if (adc_b) SC_HIP(c, ws.adc.ensure(adc_b));
+    if (st_b) SC_HIP(c, ws.chst.ensure(st_b));
+    EventDesc* hd = ws.h_desc.as<EventDesc>();
+    for (uint32_t i = 0; i < n; ++i) {
+        EventDesc d{};
+        if (ev[i].mem == SC_MEM_HOST) {
+            const uint64_t span = event_span(ev[i].fed_offset, n_fed);
+            if (span) std::memcpy(ws.h_zs.as<uint8_t>() + st.zs_off[i], ev[i].zs, span);
+            std::memcpy(ws.h_fo.as<uint8_t>() + st.fo_off[i], ev[i].fed_offset,
+                        sizeof(uint64_t) * (n_fed + 1));
+            d.zs = ws.zs.as<uint8_t>() + st.zs_off[i];
+            d.fed_off = reinterpret_cast<const uint64_t*>(ws.fo.as<uint8_t>() + st.fo_off[i]);
+        } else {
+            d.zs = ev[i].zs;
+            d.fed_off = ev[i].fed_offset;
+        }
+        if (out[i].mem == SC_MEM_HOST) {
+            d.cl = reinterpret_cast<sc_cluster_rec*>(ws.cl.as<uint8_t>() + st.cl_off[i]);
+            d.adc = reinterpret_cast<uint16_t*>(ws.adc.as<uint8_t>() + st.adc_off[i]);
+            d.chan_status = out[i].chan_status ? ws.chst.as<uint8_t>() + st.st_off[i] : nullptr;
+        } else {
+            d.cl = out[i].cl;
+            d.adc = out[i].adc;
+            d.chan_status = out[i].chan_status;
+        }
+        d.cap_cl = out[i].cap_cl;
+        d.cap_adc = out[i].cap_adc;
+        hd[i] = d;
+    }
+    if (zs_bytes) SC_HIP(c, hipMemcpyAsync(ws.zs.p, ws.h_zs.p, zs_bytes, hipMemcpyHostToDevice, s));
+    if (fo_bytes) SC_HIP(c, hipMemcpyAsync(ws.fo.p, ws.h_fo.p, fo_bytes, hipMemcpyHostToDevice, s));
+    return SC_OK;
+}
+
+FusedArgs fused_args(sc_ctx* c, Workspace& ws, uint32_t n) {
+    FusedArgs a{};
+    a.ev = ws.desc.as<EventDesc>();
+    a.res = ws.res.as<EventResult>();
+    a.tile_state = ws.state.as<unsigned long long>();
+    a.queue = ws.queue.as<uint32_t>();
+    a.cal.strip = c->d_strip;
+    a.cal.gain = c->d_gain;
+    a.cal.n_fed = c->n_fed;
+    a.cal.t_cluster = c->t_cluster;
+    a.n_ev = n;
+    a.fed_major = c->tuning.fed_major;
+    return a;
+}
+
+// The device part of a batched launch: descriptors H2D, reset, fused kernel, results D2H.
+hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bool timed) {
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ws.desc.p, ws.h_desc.p, sizeof(EventDesc) * n, hipMemcpyHostToDevice, s)))
+        return e;
+    const FusedArgs a = fused_args(c, ws, n);
+    if ((e = launch_reset(a, c->n_fed, s))) return e;
+    if (timed && (e = hipEventRecord(c->ev0, s))) return e;
+    const uint32_t grid = grid_for(c, n * c->n_fed, false);
+    if ((e = launch_fused(a, c->tuning.chunk_digis, grid, s))) return e;
+    if (timed && (e = hipEventRecord(c->ev1, s))) return e;
+    return hipMemcpyAsync(ws.h_res.p, ws.res.p, sizeof(EventResult) * n, hipMemcpyDeviceToHost, s);
+}
+
+// Replays (capturing on first use) the batched launch as a hipGraph.
+hipError_t enqueue_batch_graph(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s) {
+    const uint32_t grid = grid_for(c, n * c->n_fed, false);
+    GraphKey k{n, c->tuning.chunk_digis, grid, c->tuning.fed_major, ws.generation};
+    auto it = c->graphs.find(k);
+    hipError_t e;
+    if (it == c->graphs.end()) {
+        hipStream_t cs;
+        if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking))) return e;
+        hipGraph_t g;
+        if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal))) return e;
+        e = enqueue_batch(c, ws, n, cs, true);
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        (void)hipStreamDestroy(cs);
+        if (e) return e;
+        if (e2) return e2;
+        hipGraphExec_t ge;
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e) return e;
+        it = c->graphs.emplace(k, ge).first;
+        c->stats.graph_captures++;
+    }
+    c->stats.graph_replays++;
+    return hipGraphLaunch(it->second, s);
+}
+
+sc_status finish_batch(sc_ctx* c, Workspace& ws, const Staged& st, uint32_t n, sc_clusters* out,
+                       sc_status* ev_status, hipStream_t s) {
+    const EventResult* r = ws.h_res.as<EventResult>();
+    sc_status total = SC_OK;
+    bool any_host = false;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (r[i].flags & kResSpinTimeout)
+            return device_fail(c, hipErrorLaunchTimeOut, "fused kernel look-back wait bound");
+        out[i].n_cl = r[i].n_cl;
+        out[i].n_adc = r[i].n_adc;
+        const sc_status si = status_of(r[i], out[i]);
+        if (ev_status) ev_status[i] = si;
+        total = worst(total, si);
+        if (out[i].mem == SC_MEM_HOST) {
+            any_host = true;
+            const uint64_t ncl = std::min<uint64_t>(r[i].n_cl, out[i].cap_cl);
+            const uint64_t nadc = std::min<uint64_t>(r[i].n_adc, out[i].cap_adc);
+            if (ncl)
+                SC_HIP(c, hipMemcpyAsync(out[i].cl, ws.cl.as<uint8_t>() + st.cl_off[i],
+                                         ncl * sizeof(sc_cluster_rec), hipMemcpyDeviceToHost, s));
+            if (nadc)
+                SC_HIP(c, hipMemcpyAsync(out[i].adc, ws.adc.as<uint8_t>() + st.adc_off[i],
+                                         nadc * sizeof(uint16_t), hipMemcpyDeviceToHost, s));
+            if (out[i].chan_status)
+                SC_HIP(c, hipMemcpyAsync(out[i].chan_status, ws.chst.as<uint8_t>() + st.st_off[i],
+                                         (size_t)c->n_fed * kChannelsPerFed, hipMemcpyDeviceToHost, s));
+        }
+    }
+    if (any_host) SC_HIP(c, hipStreamSynchronize(s));
+    return total;
+}
+
+sc_status run_batch(sc_ctx* c, const sc_event* ev, uint32_t n, sc_clusters* out,
+                    sc_status* ev_status, bool allow_graph) {
+    Staged st;
+    sc_status s0 = stage_batch(c, c->ws, ev, n, out, c->stream, st);
+    if (s0 != SC_OK) return s0;
+    const bool graph = allow_graph && c->tuning.use_graph;
+    if (graph) SC_HIP(c, enqueue_batch_graph(c, c->ws, n, c->stream));
+    else       SC_HIP(c, enqueue_batch(c, c->ws, n, c->stream, true));
+    SC_HIP(c, hipStreamSynchronize(c->stream));
+    record_kernel_ms(c);
+    c->stats.launches++;
+    c->stats.events += n;
+    return finish_batch(c, c->ws, st, n, out, ev_status, c->stream);
+}
+
+// ---- autotuner cache (tiny JSON: {"<device>/<n_fed>": [chunk, waves, fed_major, graph]}) ----
+std::string tune_key(const sc_ctx* c) {
+    return c->device_name + "/" + std::to_string(c->n_fed);
+}
+
+bool load_tuning(sc_ctx* c) {
+    if (c->tune_cache.empty()) return false;
+    std::ifstream f(c->tune_cache);
+    if (!f) return false;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string txt = ss.str();
+    const std::string k = "\"" + tune_key(c) + "\"";
+    size_t p = txt.find(k);
+    if (p == std::string::npos) return false;
+    p = txt.find('[', p);
+    if (p == std::string::npos) return false;
+    unsigned a = 0, b = 0, d = 0, g = 0;
+    if (std::sscanf(txt.c_str() + p, "[%u,%u,%u,%u]", &a, &b, &d, &g) != 4) return false;
+    if (!chunk_digis_supported(a) || b < 1 || b > 32) return false;
+    c->tuning = sc_tuning{a, b, d ? 1u : 0u, g ? 1u : 0u};
+    return true;
+}
+
+void save_tuning(const sc_ctx* c) {
+    if (c->tune_cache.empty()) return;
+    std::map<std::string, std::string> entries;
+    {
+        std::ifstream f(c->tune_cache);
+        std::string line;
+        while (f && std::getline(f, line)) {
+            size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1), b = line.find('[');
+            size_t e = line.find(']');
+            if (q0 == std::string::npos || q1 == std::string::npos || b == std::string::npos ||
+                e == std::string::npos)
+                continue;
+            entries[line.substr(q0 + 1, q1 - q0 - 1)] = line.substr(b, e - b + 1);
+        }
+    }
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "[%u,%u,%u,%u]", c->tuning.chunk_digis, c->tuning.waves_per_cu,
+                  c->tuning.fed_major, c->tuning.use_graph);
+    entries[tune_key(c)] = buf;
+    std::ofstream f(c->tune_cache, std::ios::trunc);
+    f << "{\n";
+    size_t i = 0;
+    for (auto& kv : entries)
+        f << "  \"" << kv.first << "\": " << kv.second << (++i < entries.size() ? ",\n" : "\n");
+    f << "}\n";
+}
+
+}  // namespace
+
+// =============================================================================================
+// Server: continuous batching over a few streams with HBM-budget admission (paper §3: several
+// events in flight, transfers overlapped with compute).
+// =============================================================================================
+namespace {
+struct Req {
+    uint64_t id = 0;
+    sc_event ev{};
+    sc_clusters* out = nullptr;
+    std::vector<uint8_t> zs_copy;        // host ZS copied at submit
+    std::vector<uint64_t> fo_copy;
+    size_t bytes = 0;                     // budget reservation
+    sc_status status = SC_PENDING;
+    std::chrono::steady_clock::time_point t_submit;
+};
+}  // namespace
+
+struct Server {
+    sc_ctx* c;
+    std::thread thr;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Req>> waiting;
+    std::unordered_map<uint64_t, std::shared_ptr<Req>> tickets;
+    uint64_t next_id = 1;
+    size_t budget = 0, reserved = 0;
+    bool stop = false;
+    struct Slot {
+        hipStream_t s = nullptr;
+        Workspace ws;
+        hipEvent_t done = nullptr;
+        std::vector<std::shared_ptr<Req>> batch;
+        Staged st;
+        bool busy = false;
+    };
+    std::vector<Slot> slots;
+    sc_status init_error = SC_OK;
+
+    explicit Server(sc_ctx* ctx) : c(ctx) {}
+
+    sc_status start() {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 1ull << 32;
+        budget = c->opt.hbm_budget ? c->opt.hbm_budget : free_b / 4;
+        const uint32_t ns = std::max<uint32_t>(1, c->opt.n_streams);
+        slots.resize(ns);
+        for (auto& sl : slots) {
+            if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+                return SC_ERR_DEVICE;
+        }
+        thr = std::thread([this] { loop(); });
+        return SC_OK;
+    }
+
+    ~Server() {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            stop = true;
+        }
+        cv_work.notify_all();
+        if (thr.joinable()) thr.join();
+        for (auto& sl : slots) {
+            if (sl.s) (void)hipStreamSynchronize(sl.s);
+            sl.ws.release();
+            if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.s) (void)hipStreamDestroy(sl.s);
+        }
+    }
+
+    static size_t reservation(const sc_ctx* c, const sc_event& ev, const sc_clusters& o) {
+        size_t b = sizeof(unsigned long long) * c->n_fed + sizeof(EventDesc) + sizeof(EventResult);
+        b += sizeof(sc_cluster_rec) * (size_t)o.cap_cl + sizeof(uint16_t) * (size_t)o.cap_adc;
+        if (o.chan_status) b += (size_t)c->n_fed * kChannelsPerFed;
+        if (ev.mem == SC_MEM_HOST) b += event_span(ev.fed_offset, c->n_fed);
+        return b;
+    }
+
+    sc_status submit(const sc_event& ev, sc_clusters* out, uint64_t* ticket) {
+        auto r = std::make_shared<Req>();
+        r->bytes = reservation(c, ev, *out);
+        if (r->bytes > budget) return fail(c, SC_ERR_BUDGET, "event larger than the HBM budget");
+        r->ev = ev;
+        r->out = out;
+        if (ev.mem == SC_MEM_HOST) {
+            const uint64_t span = event_span(ev.fed_offset, c->n_fed);
+            r->zs_copy.assign(ev.zs, ev.zs + span);
+            r->fo_copy.assign(ev.fed_offset, ev.fed_offset + c->n_fed + 1);
+            r->ev.zs = r->zs_copy.data();
+            r->ev.fed_offset = r->fo_copy.data();
+        }
+        r->t_submit = std::chrono::steady_clock::now();
+        {
+            std::lock_guard<std::mutex> g(mu);
+            if (waiting.size() >= std::max<uint32_t>(1, c->opt.queue_depth)) {
+                c->stats.server_rejected_again++;
+                return SC_ERR_AGAIN;
+            }
+            r->id = next_id++;
+            tickets[r->id] = r;
+            waiting.push_back(r);
+            *ticket = r->id;
+        }
+        cv_work.notify_one();
+        return SC_OK;
+    }
+
+    sc_status poll(uint64_t ticket, int64_t timeout_us) {
+        std::unique_lock<std::mutex> g(mu);
+        auto it = tickets.find(ticket);
+        if (it == tickets.end()) return SC_ERR_UNKNOWN_TICKET;
+        auto r = it->second;
+        auto done = [&] { return r->status != SC_PENDING; };
+        if (!done()) {
+            if (timeout_us < 0) cv_done.wait(g, done);
+            else if (timeout_us > 0)
+                cv_done.wait_for(g, std::chrono::microseconds(timeout_us), done);
+        }
+        if (!done()) return SC_PENDING;
+        tickets.erase(ticket);
+        return r->status;
+    }
+
+    // launch what is waiting on a free slot, within the budget
+    bool launch_some() {
+        Slot* slot = nullptr;
+        for (auto& sl : slots)
+            if (!sl.busy) { slot = &sl; break; }
+        if (!slot) return false;
+        std::vector<std::shared_ptr<Req>> batch;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            const uint32_t maxb = std::max<uint32_t>(1, c->opt.max_batch);
+            while (!waiting.empty() && batch.size() < maxb &&
+                   reserved + waiting.front()->bytes <= budget) {
+                reserved += waiting.front()->bytes;
+                batch.push_back(waiting.front());
+                waiting.pop_front();
+            }
+        }
+        if (batch.empty()) return false;
+        const uint32_t n = (uint32_t)batch.size();
+        std::vector<sc_event> evs(n);
+        std::vector<sc_clusters> outs(n);
+        for (uint32_t i = 0; i < n; ++i) {
+            evs[i] = batch[i]->ev;
+            outs[i] = *batch[i]->out;
+        }
+        sc_status st = stage_batch(c, slot->ws, evs.data(), n, outs.data(), slot->s, slot->st);
+        hipError_t e = hipSuccess;
+        if (st == SC_OK) e = enqueue_batch(c, slot->ws, n, slot->s, false);
+        if (st == SC_OK && e == hipSuccess) e = hipEventRecord(slot->done, slot->s);
+        if (st != SC_OK || e != hipSuccess) {
+            if (e != hipSuccess) device_fail(c, e, "server launch");
+            complete(batch, SC_ERR_DEVICE);
+            return true;
+        }
+        slot->batch = std::move(batch);
+        slot->busy = true;
+        c->stats.server_batches++;
+        c->stats.server_events += n;
+        return true;
+    }
+
+    void complete(std::vector<std::shared_ptr<Req>>& batch, sc_status forced) {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto& r : batch) {
+            reserved -= r->bytes;
+            if (forced != SC_OK) r->status = forced;
+        }
+        batch.clear();
+        cv_done.notify_all();
+    }
+
+    bool reap() {
+        bool any = false;
+        for (auto& sl : slots) {
+            if (!sl.busy) continue;
+            hipError_t q = hipEventQuery(sl.done);
+            if (q == hipErrorNotReady) continue;
+            any = true;
+            const uint32_t n = (uint32_t)sl.batch.size();
+            if (q != hipSuccess) {
+                device_fail(c, q, "server batch");
+                complete(sl.batch, SC_ERR_DEVICE);
+                sl.busy = false;
+                continue;
+            }
+            std::vector<sc_clusters> outs(n);
+            for (uint32_t i = 0; i < n; ++i) outs[i] = *sl.batch[i]->out;
+            std::vector<sc_status> sts(n, SC_OK);
+            sc_status fs = finish_batch(c, sl.ws, sl.st, n, outs.data(), sts.data(), sl.s);
+            {
+                std::lock_guard<std::mutex> g(mu);
+                for (uint32_t i = 0; i < n; ++i) {
+                    sl.batch[i]->out->n_cl = outs[i].n_cl;
+                    sl.batch[i]->out->n_adc = outs[i].n_adc;
+                    sl.batch[i]->status = fs == SC_ERR_DEVICE ? SC_ERR_DEVICE : sts[i];
+                }
+            }
+            complete(sl.batch, SC_OK);
+            sl.busy = false;
+        }
+        return any;
+    }
+
+    void loop() {
+        if (hipSetDevice(c->device) != hipSuccess) return;
+        for (;;) {
+            bool progressed = reap();
+            while (launch_some()) progressed = true;
+            std::unique_lock<std::mutex> g(mu);
+            if (stop) break;
+            bool busy = false;
+            for (auto& sl : slots) busy |= sl.busy;
+            if (!progressed) {
+                if (busy) cv_work.wait_for(g, std::chrono::microseconds(20));
+                else cv_work.wait_for(g, std::chrono::milliseconds(5),
+                                      [&] { return stop || !waiting.empty(); });
+            }
+        }
+    }
+};
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+void sc_default_options(sc_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->device = 0;
+    o->stream = nullptr;
+    o->hbm_budget = 0;
+    o->max_batch = 64;
+    o->n_streams = 2;
+    o->queue_depth = 4096;
+    o->tune_cache = nullptr;
+}
+
+sc_status sc_create(const sc_calib* cal, const sc_options* opt_in, sc_ctx** out) {
+    if (!out) return fail(nullptr, SC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cal || !cal->noise || !cal->gain || !cal->bad)
+        return fail(nullptr, SC_ERR_INVALID_ARG, "calibration pointers");
+    if (cal->n_fed == 0 || cal->n_fed > 20000)
+        return fail(nullptr, SC_ERR_INVALID_ARG, "n_fed must be in 1..20000");
+    for (float t : {cal->t_seed, cal->t_channel, cal->t_cluster})
+        if (!(t >= 0.0f) || t == __builtin_inff())
+            return fail(nullptr, SC_ERR_INVALID_ARG, "thresholds must be finite and >= 0");
+    sc_options opt;
+    sc_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || opt.device < 0 || opt.device >= ndev)
+        return fail(nullptr, SC_ERR_INVALID_ARG, "no such HIP device");
+    if (hipSetDevice(opt.device) != hipSuccess) return fail(nullptr, SC_ERR_DEVICE, "hipSetDevice");
+    auto c = std::make_unique<sc_ctx>();
+    c->device = opt.device;
+    c->opt = opt;
+    c->n_fed = cal->n_fed;
+    c->t_seed = cal->t_seed;
+    c->t_channel = cal->t_channel;
+    c->t_cluster = cal->t_cluster;
+    if (opt.tune_cache) c->tune_cache = opt.tune_cache;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, opt.device) != hipSuccess)
+        return fail(nullptr, SC_ERR_DEVICE, "hipGetDeviceProperties");
+    c->n_cu = prop.multiProcessorCount;
+    c->device_name = prop.gcnArchName;
+    c->tuning = sc_tuning{2048, 32, 1, 1};
+    load_tuning(c.get());
+    if (opt.stream) {
+        c->stream = static_cast<hipStream_t>(opt.stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(nullptr, SC_ERR_DEVICE, "hipStreamCreate");
+        c->own_stream = true;
+    }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+        return fail(nullptr, SC_ERR_DEVICE, "hipEventCreate");
+    const size_t n_strips = (size_t)cal->n_fed * kChannelsPerFed * kStripsPerChannel;
+    const size_t n_apv = n_strips / kStripsPerApv;
+    float* d_noise = nullptr;
+    uint8_t* d_bad = nullptr;
+    hipError_t e = hipMalloc(&c->d_strip, sizeof(uint2) * n_strips);
+    if (e == hipSuccess) e = hipMalloc(&c->d_gain, sizeof(float) * n_apv);
+    if (e == hipSuccess) e = hipMalloc(&d_noise, sizeof(float) * n_strips);
+    if (e == hipSuccess) e = hipMalloc(&d_bad, n_strips);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_noise, cal->noise, sizeof(float) * n_strips, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_gain, cal->gain, sizeof(float) * n_apv, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_bad, cal->bad, n_strips, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = launch_derive_calib(d_noise, c->d_gain, d_bad, cal->n_fed, cal->t_seed,
+                                cal->t_channel, c->d_strip, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (d_noise) (void)hipFree(d_noise);
+    if (d_bad) (void)hipFree(d_bad);
+    if (e == hipSuccess) e = c->ws.ensure_batch(64, c->n_fed);
+    if (e != hipSuccess) {
+        std::string msg = std::string("calibration upload: ") + hipGetErrorString(e);
+        sc_destroy(c.release());
+        return fail(nullptr, e == hipErrorOutOfMemory ? SC_ERR_NOMEM : SC_ERR_DEVICE, msg);
+    }
+    *out = c.release();
+    return SC_OK;
+}
+
+void sc_destroy(sc_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    c->server.reset();
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->ws.release();
+    if (c->d_strip) (void)hipFree(c->d_strip);
+    if (c->d_gain) (void)hipFree(c->d_gain);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+sc_status sc_unpack(sc_ctx* c, const sc_event* ev, uint8_t* adc_dense, uint8_t* chan_status,
+                    sc_mem out_mem) {
+    if (!c) return SC_ERR_INVALID_ARG;
+    if (c->poisoned) return SC_ERR_DEVICE;
+    if (!ev || !adc_dense) return fail(c, SC_ERR_INVALID_ARG, "NULL argument");
+    sc_status s0 = check_event(c, *ev);
+    if (s0 != SC_OK) return s0;
+    if (out_mem == SC_MEM_DEVICE && (reinterpret_cast<uintptr_t>(adc_dense) & 15u))
+        return fail(c, SC_ERR_INVALID_ARG, "device dense buffer must be 16-byte aligned");
+    SC_HIP(c, hipSetDevice(c->device));
+    const size_t dense_b = (size_t)c->n_fed * kChannelsPerFed * kStripsPerChannel;
+    const size_t st_b = (size_t)c->n_fed * kChannelsPerFed;
+    Workspace& ws = c->ws;
+    SC_HIP(c, ws.ensure_batch(1, c->n_fed));
+    const uint8_t* zs = ev->zs;
+    const uint64_t* fo = ev->fed_offset;
+    if (ev->mem == SC_MEM_HOST) {
+        const uint64_t span = event_span(ev->fed_offset, c->n_fed);
+        SC_HIP(c, ws.zs.ensure(span + 16));
+        SC_HIP(c, ws.fo.ensure(sizeof(uint64_t) * (c->n_fed + 1)));
+        if (span) SC_HIP(c, hipMemcpyAsync(ws.zs.p, ev->zs, span, hipMemcpyHostToDevice, c->stream));
+        SC_HIP(c, hipMemcpyAsync(ws.fo.p, ev->fed_offset, sizeof(uint64_t) * (c->n_fed + 1),
+                                 hipMemcpyHostToDevice, c->stream));
+        zs = ws.zs.as<uint8_t>();
+        fo = ws.fo.as<uint64_t>();
+    }
+    uint8_t* d_dense = adc_dense;
+    uint8_t* d_st = chan_status;
+    if (out_mem == SC_MEM_HOST) {
+        SC_HIP(c, ws.dense.ensure(dense_b));
+        d_dense = ws.dense.as<uint8_t>();
+        if (chan_status) {
+            SC_HIP(c, ws.chst.ensure(st_b));
+            d_st = ws.chst.as<uint8_t>();
+        }
+    }
+    FusedArgs a = fused_args(c, ws, 1);
+    SC_HIP(c, launch_reset(a, 0, c->stream));
+    SC_HIP(c, hipEventRecord(c->ev0, c->stream));
+    SC_HIP(c, launch_unpack(zs, fo, c->n_fed, d_dense, d_st, a.res, c->stream));
+    SC_HIP(c, hipEventRecord(c->ev1, c->stream));
+    SC_HIP(c, hipMemcpyAsync(ws.h_res.p, ws.res.p, sizeof(EventResult), hipMemcpyDeviceToHost, c->stream));
+    if (out_mem == SC_MEM_HOST) {
+        SC_HIP(c, hipMemcpyAsync(adc_dense, d_dense, dense_b, hipMemcpyDeviceToHost, c->stream));
+        if (chan_status)
+            SC_HIP(c, hipMemcpyAsync(chan_status, d_st, st_b, hipMemcpyDeviceToHost, c->stream));
+    }
+    SC_HIP(c, hipStreamSynchronize(c->stream));
+    record_kernel_ms(c);
+    c->stats.launches++;
+    return (ws.h_res.as<EventResult>()[0].flags & kResMalformed) ? SC_MALFORMED : SC_OK;
+}
+
+sc_status sc_cluster(sc_ctx* c, const uint8_t* adc_dense, sc_mem in_mem, sc_clusters* out) {
+    if (!c) return SC_ERR_INVALID_ARG;
+    if (c->poisoned) return SC_ERR_DEVICE;
+    if (!adc_dense || !out) return fail(c, SC_ERR_INVALID_ARG, "NULL argument");
+    sc_status s0 = check_out(c, *out);
+    if (s0 != SC_OK) return s0;
+    if (in_mem == SC_MEM_DEVICE && (reinterpret_cast<uintptr_t>(adc_dense) & 15u))
+        return fail(c, SC_ERR_INVALID_ARG, "device dense buffer must be 16-byte aligned");
+    SC_HIP(c, hipSetDevice(c->device));
+    const size_t dense_b = (size_t)c->n_fed * kChannelsPerFed * kStripsPerChannel;
+    Workspace& ws = c->ws;
+    SC_HIP(c, ws.ensure_batch(1, c->n_fed));
+    const uint8_t* d_in = adc_dense;
+    if (in_mem == SC_MEM_HOST) {
+        SC_HIP(c, ws.dense.ensure(dense_b));
+        SC_HIP(c, hipMemcpyAsync(ws.dense.p, adc_dense, dense_b, hipMemcpyHostToDevice, c->stream));
+        d_in = ws.dense.as<uint8_t>();
+    }
+    sc_clusters o = *out;
+    o.chan_status = nullptr;
+    sc_event dummy{nullptr, nullptr, SC_MEM_DEVICE};
+    Staged st;
+    s0 = stage_batch(c, ws, &dummy, 1, &o, c->stream, st);
+    if (s0 != SC_OK) return s0;
+    SC_HIP(c, hipMemcpyAsync(ws.desc.p, ws.h_desc.p, sizeof(EventDesc), hipMemcpyHostToDevice, c->stream));
+    FusedArgs a = fused_args(c, ws, 1);
+    SC_HIP(c, launch_reset(a, c->n_fed, c->stream));
+    SC_HIP(c, hipEventRecord(c->ev0, c->stream));
+    SC_HIP(c, launch_cluster_dense(d_in, a, c->tuning.chunk_digis, grid_for(c, c->n_fed, true), c->stream));
+    SC_HIP(c, hipEventRecord(c->ev1, c->stream));
+    SC_HIP(c, hipMemcpyAsync(ws.h_res.p, ws.res.p, sizeof(EventResult), hipMemcpyDeviceToHost, c->stream));
+    SC_HIP(c, hipStreamSynchronize(c->stream));
+    record_kernel_ms(c);
+    c->stats.launches++;
+    sc_status r = finish_batch(c, ws, st, 1, &o, nullptr, c->stream);
+    out->n_cl = o.n_cl;
+    out->n_adc = o.n_adc;
+    return r == SC_MALFORMED ? SC_OK : r;
+}
+
+sc_status sc_process_events(sc_ctx* c, const sc_event* ev, uint32_t n, sc_clusters* out,
+                            sc_status* ev_status) {
+    if (!c) return SC_ERR_INVALID_ARG;
+    if (c->poisoned) return SC_ERR_DEVICE;
+    if (!ev || !out || n == 0) return fail(c, SC_ERR_INVALID_ARG, "NULL argument or n == 0");
+    if ((uint64_t)n * c->n_fed > 0x7fffffffull) return fail(c, SC_ERR_INVALID_ARG, "batch too large");
+    bool all_device = true;
+    for (uint32_t i = 0; i < n; ++i) {
+        sc_status s = check_event(c, ev[i]);
+        if (s != SC_OK) return s;
+        s = check_out(c, out[i]);
+        if (s != SC_OK) return s;
+        all_device &= ev[i].mem == SC_MEM_DEVICE && out[i].mem == SC_MEM_DEVICE;
+    }
+    SC_HIP(c, hipSetDevice(c->device));
+    return run_batch(c, ev, n, out, ev_status, all_device);
+}
+
+sc_status sc_submit(sc_ctx* c, const sc_event* ev, sc_clusters* out, uint64_t* ticket) {
+    if (!c) return SC_ERR_INVALID_ARG;
+    if (c->poisoned) return SC_ERR_DEVICE;
+    if (!ev || !out || !ticket) return fail(c, SC_ERR_INVALID_ARG, "NULL argument");
+    sc_status s = check_event(c, *ev);
+    if (s != SC_OK) return s;
+    s = check_out(c, *out);
+    if (s != SC_OK) return s;
+    {
+        std::lock_guard<std::mutex> g(c->server_mu);
+        if (!c->server) {
+            if (hipSetDevice(c->device) != hipSuccess) return fail(c, SC_ERR_DEVICE, "hipSetDevice");
+            auto sv = std::make_unique<Server>(c);
+            if (sv->start() != SC_OK) return fail(c, SC_ERR_DEVICE, "server start");
+            c->server = std::move(sv);
+        }
+    }
+    return c->server->submit(*ev, out, ticket);
+}
+
+sc_status sc_poll(sc_ctx* c, uint64_t ticket, int64_t timeout_us) {
+    if (!c) return SC_ERR_INVALID_ARG;
+    Server* sv;
+    {
+        std::lock_guard<std::mutex> g(c->server_mu);
+        sv = c->server.get();
+    }
+    if (!sv) return SC_ERR_UNKNOWN_TICKET;
+    return sv->poll(ticket, timeout_us);
+}
+
+sc_status sc_get_tuning(const sc_ctx* c, sc_tuning* t) {
+    if (!c || !t) return SC_ERR_INVALID_ARG;
+    *t = c->tuning;
+    return SC_OK;
+}
+
+sc_status sc_set_tuning(sc_ctx* c, const sc_tuning* t) {
+    if (!c || !t) return SC_ERR_INVALID_ARG;
+    if (!chunk_digis_supported(t->chunk_digis) || t->waves_per_cu < 1 || t->waves_per_cu > 32)
+        return fail(c, SC_ERR_INVALID_ARG, "unsupported tuning");
+    c->tuning = *t;
+    c->tuning.fed_major = t->fed_major ? 1 : 0;
+    c->tuning.use_graph = t->use_graph ? 1 : 0;
+    return SC_OK;
+}
+
+sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best) {
+    if (!c) return SC_ERR_INVALID_ARG;
+    if (c->poisoned) return SC_ERR_DEVICE;
+    if (!ev || n == 0) return fail(c, SC_ERR_INVALID_ARG, "no events");
+    for (uint32_t i = 0; i < n; ++i) {
+        sc_status s = check_event(c, ev[i]);
+        if (s != SC_OK) return s;
+    }
+    SC_HIP(c, hipSetDevice(c->device));
+    // outputs sized by the safe bound: clusters and member ADCs <= digis <= ZS bytes
+    std::vector<uint32_t> cap(n);
+    std::vector<uint64_t> off_cl(n), off_adc(n);
+    uint64_t tot_cl = 0, tot_adc = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        uint64_t span;
+        if (ev[i].mem == SC_MEM_HOST) {
+            span = event_span(ev[i].fed_offset, c->n_fed);
+        } else {
+            std::vector<uint64_t> fo(c->n_fed + 1);
+            SC_HIP(c, hipMemcpy(fo.data(), ev[i].fed_offset, sizeof(uint64_t) * fo.size(), hipMemcpyDeviceToHost));
+            span = event_span(fo.data(), c->n_fed);
+        }
+        cap[i] = (uint32_t)std::min<uint64_t>(span, 0xffffffffull);
+        off_cl[i] = tot_cl;
+        off_adc[i] = tot_adc;
+        tot_cl += align_up((uint64_t)cap[i] * sizeof(sc_cluster_rec), 256);
+        tot_adc += align_up((uint64_t)cap[i] * 2, 256);
+    }
+    DevBuf bcl, badc;
+    SC_HIP(c, bcl.ensure(tot_cl));
+    SC_HIP(c, badc.ensure(tot_adc));
+    std::vector<sc_clusters> out(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        out[i] = sc_clusters{reinterpret_cast<sc_cluster_rec*>(bcl.as<uint8_t>() + off_cl[i]), cap[i], 0,
+                             reinterpret_cast<uint16_t*>(badc.as<uint8_t>() + off_adc[i]), cap[i], 0,
+                             nullptr, SC_MEM_DEVICE};
+    }
+    const sc_tuning saved = c->tuning;
+    std::vector<sc_tuning> cands;
+    for (uint32_t d : {1024u, 1536u, 2048u, 3072u})
+        for (uint32_t fm : {0u, 1u}) {
+            const int occ = fused_blocks_per_cu(d, false);
+            for (uint32_t w : {(uint32_t)occ, (uint32_t)std::max(1, occ / 2)})
+                cands.push_back(sc_tuning{d, w, fm, 0});
+        }
+    std::vector<uint8_t> ref_cl, ref_adc, cur_cl, cur_adc;
+    double best_ms = 1e30;
+    sc_tuning best_t = saved;
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        c->tuning = cands[ci];
+        std::vector<float> times;
+        for (int rep = 0; rep < 4; ++rep) {
+            sc_status s = run_batch(c, ev, n, out.data(), nullptr, false);
+            if (s < 0) {
+                c->tuning = saved;
+                bcl.release();
+                badc.release();
+                return s;
+            }
+            if (rep > 0) times.push_back((float)c->stats.last_kernel_ms);
+        }
+        std::sort(times.begin(), times.end());
+        const double ms = times[times.size() / 2];
+        // identical results for every choice
+        cur_cl.resize(tot_cl);
+        cur_adc.resize(tot_adc);
+        SC_HIP(c, hipMemcpy(cur_cl.data(), bcl.p, tot_cl, hipMemcpyDeviceToHost));
+        SC_HIP(c, hipMemcpy(cur_adc.data(), badc.p, tot_adc, hipMemcpyDeviceToHost));
+        if (ci == 0) {
+            ref_cl = cur_cl;
+            ref_adc = cur_adc;
+        } else {
+            for (uint32_t i = 0; i < n; ++i) {
+                const size_t ncl = std::min(out[i].n_cl, cap[i]) * sizeof(sc_cluster_rec);
+                const size_t nad = std::min(out[i].n_adc, cap[i]) * 2;
+                if (std::memcmp(cur_cl.data() + off_cl[i], ref_cl.data() + off_cl[i], ncl) ||
+                    std::memcmp(cur_adc.data() + off_adc[i], ref_adc.data() + off_adc[i], nad)) {
+                    c->tuning = saved;
+                    bcl.release();
+                    badc.release();
+                    return fail(c, SC_ERR_DEVICE, "autotune: tuning choices disagree");
+                }
+            }
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_t = cands[ci];
+        }
+    }
+    bcl.release();
+    badc.release();
+    best_t.use_graph = saved.use_graph;
+    c->tuning = best_t;
+    save_tuning(c);
+    if (best) *best = best_t;
+    return SC_OK;
+}
+
+sc_status sc_get_stats(const sc_ctx* c, sc_stats* s) {
+    if (!c || !s) return SC_ERR_INVALID_ARG;
+    *s = c->stats;
+    return SC_OK;
+}
+
+const char* sc_last_error(const sc_ctx* c) {
+    if (!c) return g_create_error.c_str();
+    std::lock_guard<std::mutex> g(c->err_mu);
+    thread_local std::string copy;
+    copy = c->last_error;
+    return copy.c_str();
+}
+
+}  // extern "C"
