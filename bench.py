@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark of the strip unpacking + three-threshold clustering path on one MI355X.
+
+Headline step: one fused, persistent launch (sc_process_events) over a batch of 64 synthetic
+full-detector events (440 FEDs x 96 channels x 256 strips each; per-event occupancy log-uniform in
+[0.5%, 5%]), inputs resident in HBM before the timed region, outputs written to HBM. Beside it:
+the plain per-event GPU path (sc_unpack then sc_cluster, one full-detector event at 1.5%
+occupancy per call), the same events through the fused kernel one at a time, and the oracle timed
+on host cores on a bounded sample.
+
+Prints one JSON line. ``--gpus`` above 1 is refused: the path runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import fedgen  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_kernel_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2101_11489_amd", "csrc", "sc_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(events, counts, n_fed):
+    """Bytes a launch must move at least once: ZS input and FED offsets, cluster records and
+    member ADCs out, and the calibration of strips holding a digi in at least one event of the
+    launch (4 B noise + 1 bit bad flag per strip, 4 B gain per APV)."""
+    b = 0.0
+    touched = np.zeros(n_fed * 96 * 256, dtype=bool)
+    for ev, (ncl, nadc) in zip(events, counts):
+        b += ev.zs.size + 8 * (n_fed + 1) + 16 * ncl + 2 * nadc
+        touched |= ev.dense > 0
+    n_strips = int(touched.sum())
+    n_apv = int(touched.reshape(-1, 128).any(axis=1).sum())
+    b += n_strips * (4 + 1 / 8) + 4 * n_apv
+    return b
+
+
+def kernel_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(n_launch_bytes_key):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on the
+    current kernel source; else None."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha() or t.get("workload") != n_launch_bytes_key:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--plain-events", type=int, default=8)
+    ap.add_argument("--cpu-sample", type=int, default=24,
+                    help="events of the batch the oracle processes for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="chunk_digis,waves_per_cu,fed_major,use_graph")
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs the path on one GPU only (got --gpus {args.gpus}); events shard "
+              "across GPUs with host-side dispatch and no device exchange, so per-GPU throughput "
+              "is the single-GPU figure.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2101_11489_amd as sc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev_name = torch.cuda.get_device_name(0)
+
+    # ---- workload: 64 full-detector events, occupancy log-uniform in [0.5%, 5%] -------------
+    cfg = fedgen.CONFIGS[2]
+    t0 = time.time()
+    cal = fedgen.make_calibration(cfg)
+    events = fedgen.make_events(cfg, cal, range(args.batch), workers=args.workers)
+    log(f"generated {len(events)} events in {time.time() - t0:.1f}s; "
+        f"ZS {sum(e.zs.size for e in events) / 1e6:.1f} MB")
+
+    stream = torch.cuda.Stream()
+    ctx = sc.Context(cal.noise, cal.gain, cal.bad, device=0, stream=stream)
+    if args.tuning:
+        c, w, f, g = (int(x) for x in args.tuning.split(","))
+        ctx.tuning = {"chunk_digis": c, "waves_per_cu": w, "fed_major": f, "use_graph": g}
+    devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in events]
+    outs = [ctx.output(*sc.safe_caps(d)) for d in devs]
+    torch.cuda.synchronize()
+    if args.autotune:
+        t = ctx.autotune(devs)
+        log(f"autotuned: {t}")
+
+    # ---- warm-up, then a sampled parity check at full size ---------------------------------
+    for _ in range(args.warmup):
+        ctx.process_events(devs, outs)
+    parity = "skipped"
+    try:
+        import oracle
+        ok = True
+        for i in (0, len(events) - 1):
+            ref = oracle.process_event(events[i].zs, events[i].fed_offset, cal.noise, cal.gain,
+                                       cal.bad)
+            cl, adc, _ = outs[i].to_numpy()
+            ok &= np.array_equal(cl, ref.cl) and np.array_equal(adc, ref.adc)
+        parity = "bit-exact (2 sampled events)" if ok else "MISMATCH"
+    except Exception as ex:  # the oracle is optional at bench time
+        parity = f"skipped ({ex})"
+    log(f"parity: {parity}")
+
+    # ---- timed region ------------------------------------------------------------------------
+    step_ms, kern_ms = [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        ctx.process_events(devs, outs)       # synchronous: returns when results are in HBM
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+        kern_ms.append(ctx.stats()["last_kernel_ms"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+
+    n_fed = cfg.n_fed
+    counts = [(o.n_cl, o.n_adc) for o in outs]
+    n_ev = len(events)
+    ev_per_s = n_ev * args.steps / elapsed
+    ms_per_step = elapsed / args.steps * 1e3
+    kern_valid = [k for k in kern_ms if k > 0]
+    kern_avg = statistics.mean(kern_valid) if kern_valid else float("nan")
+    b_alg = algorithmic_bytes(events, counts, n_fed)
+    achieved = b_alg / (kern_avg * 1e-3) / 1e9 if kern_valid else None
+    tuning = ctx.tuning
+    log(f"batched: {ev_per_s:.0f} events/s, {ms_per_step:.3f} ms/step, kernel {kern_avg:.3f} ms, "
+        f"B_alg {b_alg / 1e6:.1f} MB/launch -> {achieved} GB/s; tuning {tuning}")
+
+    # ---- the plain per-event path (sc_unpack + sc_cluster), full detector at 1.5% -----------
+    plain = None
+    if not args.no_plain:
+        cfg1 = fedgen.CONFIGS[1]
+        cal1 = fedgen.make_calibration(cfg1)
+        ev1 = fedgen.make_events(cfg1, cal1, range(args.plain_events), workers=args.workers)
+        ctx1 = sc.Context(cal1.noise, cal1.gain, cal1.bad, device=0, stream=stream)
+        d1 = [sc.Event(e.zs, e.fed_offset).to_device() for e in ev1]
+        o1 = [ctx1.output(*sc.safe_caps(d)) for d in d1]
+        dense = ctx1.dense_buffer()
+        for d, o in zip(d1[:2], o1[:2]):      # warm-up
+            ctx1.unpack(d, dense)
+            ctx1.cluster(dense, o)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        pk = []
+        for d, o in zip(d1, o1):
+            ctx1.unpack(d, dense)
+            ku = ctx1.stats()["last_kernel_ms"]
+            ctx1.cluster(dense, o)
+            pk.append(ku + ctx1.stats()["last_kernel_ms"])
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - tp
+        # the fused kernel, one event per launch
+        tf = time.perf_counter()
+        fk = []
+        for d, o in zip(d1, o1):
+            ctx1.process_events([d], [o])
+            fk.append(ctx1.stats()["last_kernel_ms"])
+        torch.cuda.synchronize()
+        single_s = time.perf_counter() - tf
+        # the same events as one batch
+        ctx1.process_events(d1, o1)
+        tb = time.perf_counter()
+        for _ in range(5):
+            ctx1.process_events(d1, o1)
+        torch.cuda.synchronize()
+        batch1_s = (time.perf_counter() - tb) / 5
+        b1 = algorithmic_bytes(ev1, [(o.n_cl, o.n_adc) for o in o1], cfg1.n_fed)
+        plain = {
+            "workload": f"{len(ev1)} full-detector events at 1.5% occupancy, one per call",
+            "plain_unpack_then_cluster_events_per_s": len(ev1) / plain_s,
+            "plain_kernel_ms_per_event": statistics.mean(pk),
+            "fused_one_event_per_launch_events_per_s": len(ev1) / single_s,
+            "fused_one_event_kernel_ms": statistics.mean(fk),
+            f"fused_batch_of_{len(ev1)}_events_per_s": len(ev1) / batch1_s,
+            "hbm_frac_fused_one_event": (b1 / len(ev1)) / (statistics.mean(fk) * 1e-3) / 1e9
+                                         / HBM_PEAK_GBS,
+        }
+        log(f"plain: {plain}")
+        ctx1.close()
+
+    # ---- CPU baseline: the oracle on a bounded sample, one host core ------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n_s = min(args.cpu_sample, len(events))
+        scratch = np.empty(n_fed * 96 * 256, np.uint8)
+        cl = np.empty(4_000_000, dtype=oracle.CLUSTER_DTYPE)
+        adc = np.empty(8_000_000, dtype=np.uint16)
+        tc = time.perf_counter()
+        for e in events[:n_s]:
+            oracle.process_event_raw(e.zs, e.fed_offset, cal.noise, cal.gain, cal.bad, scratch,
+                                     cl, adc)
+        cpu_s = time.perf_counter() - tc
+        cpu = {"value": n_s / cpu_s, "unit": "events/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {n_s} of the {n_ev} batch events, single-threaded C oracle, "
+                         f"{cpu_s:.1f} s"}
+        log(f"cpu baseline: {cpu}")
+
+    traffic = load_traffic(f"config2-batch{n_ev}")
+    line = {
+        "metric": "events/s, unpack + three-threshold clustering, batched full-detector events",
+        "value": ev_per_s,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched: {n_ev} full-detector events per fused persistent launch "
+                        "(440 FEDs x 96 ch x 256 strips, occupancy log-uniform 0.5-5%)",
+            "n_fed": n_fed, "events_per_launch": n_ev,
+            "zs_mb_per_launch": round(sum(e.zs.size for e in events) / 1e6, 2),
+            "clusters_per_launch": int(sum(c for c, _ in counts)),
+            "tuning": tuning, "device": dev_name,
+        },
+        "strips_per_s": ev_per_s * n_fed * 96 * 256,
+        "digis_per_s": sum(e.n_digis for e in events) * args.steps / elapsed,
+        "latency_ms_p50": float(np.percentile(step_ms, 50)),
+        "latency_ms_p99": float(np.percentile(step_ms, 99)),
+        "kernel_ms": kern_avg,
+        "parity": parity,
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": b_alg,
+            "kernel": "fused_kernel",
+        },
+        "plain_path": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,262 @@
+"""GPU: full-size events, batching, graphs, overflow, edge cases and the server, against the oracle.
+
+Bar: clusters, ranges, charges, member ADCs bit-exact; barycenters within 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+import fedgen
+import oracle
+from helpers import NS, calib_arrays, event_from_runs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2101_11489_amd as sc  # noqa: E402
+from gpu_common import compare_clusters, make_ctx, run_fused  # noqa: E402
+
+
+def _oracle(ev, cal):
+    return oracle.process_event(ev.zs, ev.fed_offset, cal.noise, cal.gain, cal.bad)
+
+
+@pytest.fixture(scope="module")
+def full():
+    """Config-2 detector (440 FEDs) with 8 events of uneven occupancy, and their oracle output."""
+    cfg = fedgen.CONFIGS[2]
+    cal = fedgen.make_calibration(cfg)
+    evs = fedgen.make_events(cfg, cal, range(8), workers=8)
+    refs = [_oracle(e, cal) for e in evs]
+    ctx = make_ctx(cal.noise, cal.gain, cal.bad)
+    yield cal, evs, refs, ctx
+    ctx.close()
+
+
+def test_full_detector_batch_exact(full):
+    cal, evs, refs, ctx = full
+    ctx.tuning = {"use_graph": 0}
+    results, rc, sts, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs])
+    assert rc == sc.SC_OK
+    for i, (res, ref) in enumerate(zip(results, refs)):
+        compare_clusters(res[0], res[1], ref, f"event {i} occ {evs[i].occ:.4f}")
+    ctx.tuning = {"use_graph": 1}
+
+
+def test_event_alone_equals_event_in_any_batch(full):
+    cal, evs, refs, ctx = full
+    pairs = [(e.zs, e.fed_offset) for e in evs]
+    alone, _, _, _ = run_fused(ctx, [pairs[3]])
+    mixed, _, _, _ = run_fused(ctx, [pairs[5], pairs[3], pairs[0]])
+    rev, _, _, _ = run_fused(ctx, pairs[::-1])
+    for got in (alone[0], mixed[1], rev[len(pairs) - 1 - 3]):
+        np.testing.assert_array_equal(got[0], alone[0][0])
+        np.testing.assert_array_equal(got[1], alone[0][1])
+    compare_clusters(alone[0][0], alone[0][1], refs[3], "alone")
+
+
+def test_graph_replays_match_eager(full):
+    cal, evs, refs, ctx = full
+    devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs[:4]]
+    outs = [ctx.output(*sc.safe_caps(d)) for d in devs]
+    ctx.tuning = {"use_graph": 1}
+    before = ctx.stats()
+    for rep in range(5):
+        for o in outs:                  # eager torch work between replays
+            o.cl.zero_()
+            o.adc.zero_()
+        torch.cuda.synchronize()
+        ctx.process_events(devs, outs)
+        for o, ref in zip(outs, refs[:4]):
+            cl, adc, _ = o.to_numpy()
+            compare_clusters(cl, adc, ref, f"replay {rep}")
+    after = ctx.stats()
+    assert after["graph_replays"] - before["graph_replays"] == 5
+    assert after["graph_captures"] - before["graph_captures"] <= 1
+
+
+def test_overflow_then_regrow(full):
+    cal, evs, refs, ctx = full
+    ev = sc.Event(evs[1].zs, evs[1].fed_offset).to_device()
+    need_cl, need_adc = refs[1].cl.size, refs[1].adc.size
+    small = ctx.output(need_cl // 3, need_adc // 2)
+    rc, sts = ctx.process_events([ev], [small])
+    assert rc == sc.SC_ERR_OVERFLOW and sts == [sc.SC_ERR_OVERFLOW]
+    assert (small.n_cl, small.n_adc) == (need_cl, need_adc)
+    cl, adc, _ = small.to_numpy()
+    np.testing.assert_array_equal(cl, refs[1].cl[:need_cl // 3])     # the prefix is valid
+    np.testing.assert_array_equal(adc, refs[1].adc[:need_adc // 2])
+    big = ctx.output(small.n_cl, small.n_adc)                          # exactly the needs
+    rc, _ = ctx.process_events([ev], [big])
+    assert rc == sc.SC_OK
+    compare_clusters(*big.to_numpy()[:2], refs[1], "regrown")
+
+
+def test_host_and_device_mixed_batch(full):
+    cal, evs, refs, ctx = full
+    e_dev = sc.Event(evs[2].zs, evs[2].fed_offset).to_device()
+    e_host = sc.Event(evs[4].zs, evs[4].fed_offset)
+    o_dev = ctx.output(*sc.safe_caps(e_host), device=True)
+    o_host = ctx.output(*sc.safe_caps(e_host), device=False, chan_status=True)
+    ctx.process_events([e_host, e_dev], [o_dev, o_host])
+    compare_clusters(*o_dev.to_numpy()[:2], refs[4], "host event -> device output")
+    cl, adc, st = o_host.to_numpy()
+    compare_clusters(cl, adc, refs[2], "device event -> host output")
+    assert not st.any()
+
+
+def test_stress_distribution_and_overflow_batch():
+    cfg = fedgen.CONFIGS[4].with_(n_fed=60)
+    cal = fedgen.make_calibration(cfg)
+    evs = fedgen.make_events(cfg, cal, range(6), workers=6)
+    refs = [_oracle(e, cal) for e in evs]
+    with make_ctx(cal.noise, cal.gain, cal.bad) as ctx:
+        # capacities sized for a lighter workload: some events overflow, the rest are exact
+        caps = (int(np.median([r.cl.size for r in refs])), int(np.median([r.adc.size for r in refs])))
+        results, rc, sts, outs = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs], caps=caps)
+        assert rc == sc.SC_ERR_OVERFLOW
+        for i, (st, o, ref) in enumerate(zip(sts, outs, refs)):
+            assert (o.n_cl, o.n_adc) == (ref.cl.size, ref.adc.size)
+            if st == sc.SC_OK:
+                compare_clusters(*o.to_numpy()[:2], ref, f"stress {i}")
+            else:
+                assert ref.cl.size > caps[0] or ref.adc.size > caps[1]
+        # retry only the overflowed events with the reported sizes
+        redo = [i for i, s in enumerate(sts) if s == sc.SC_ERR_OVERFLOW]
+        assert redo
+        res2, rc2, _, _ = run_fused(ctx, [(evs[i].zs, evs[i].fed_offset) for i in redo])
+        assert rc2 == sc.SC_OK
+        for i, r in zip(redo, res2):
+            compare_clusters(r[0], r[1], refs[i], f"stress retry {i}")
+        # long clusters crossing wavefront words and the APV boundary are present
+        allcl = np.concatenate([r.cl for r in refs])
+        assert allcl["width"].max() >= 12
+
+
+def _edge_event(kind):
+    n_fed = 3
+    noise, gain, bad = calib_arrays(n_fed)
+    if kind == "all_empty":
+        runs = {}
+        zs, fo = event_from_runs(runs, n_fed)
+    elif kind == "zero_length_feds":
+        zs, fo = np.zeros(0, np.uint8), np.zeros(n_fed + 1, np.uint64)
+    elif kind == "full_fed":
+        # every channel of FED 1 fully active with one seed: 25 KB of ZS (larger than the LDS
+        # stage) and 24576 digis (many chunks)
+        runs = {96 + c: [(0, [3] * 255), (255, [4])] for c in range(96)}
+        zs, fo = event_from_runs(runs, n_fed)
+    elif kind == "alternating_fed":
+        # 128 isolated strips per channel -> 12288 clusters in one FED
+        runs = {c: [(2 * k, [5]) for k in range(128)] for c in range(96)}
+        zs, fo = event_from_runs(runs, n_fed)
+    elif kind == "multichunk_fits_stage":
+        # 20 full channels: 5 KB of ZS (fits the stage) but 5120 digis
+        runs = {192 + c: [(0, [4] + [3] * 254), (255, [3])] for c in range(20)}
+        zs, fo = event_from_runs(runs, n_fed)
+    elif kind == "garbage":
+        rng = np.random.default_rng(7)
+        zs = rng.integers(0, 256, size=30000, dtype=np.uint8)
+        fo = np.array([0, 9000, 21000, 30000], np.uint64)
+    else:
+        raise ValueError(kind)
+    return zs, fo, noise, gain, bad
+
+
+@pytest.mark.parametrize("kind", ["all_empty", "zero_length_feds", "full_fed", "alternating_fed",
+                                  "multichunk_fits_stage", "garbage"])
+@pytest.mark.parametrize("chunk", [768, 2048, 3072])
+def test_edge_cases(kind, chunk):
+    zs, fo, noise, gain, bad = _edge_event(kind)
+    ref = oracle.process_event(zs, fo, noise, gain, bad)
+    with make_ctx(noise, gain, bad) as ctx:
+        ctx.tuning = {"chunk_digis": chunk}
+        caps = (max(ref.cl.size, 1), max(ref.adc.size, 1))
+        (res,), rc, sts, _ = run_fused(ctx, [(zs, fo)], caps=caps, chan_status=True)
+        compare_clusters(res[0], res[1], ref, kind)
+        np.testing.assert_array_equal(res[2], ref.chan_status)
+        # plain path on the same input
+        dense, _ = ctx.unpack(sc.Event(zs, fo).to_device())
+        ref_dense, _, _ = oracle.unpack(zs, fo)
+        np.testing.assert_array_equal(dense.cpu().numpy(), ref_dense)
+        out = ctx.output(*caps)
+        ctx.cluster(dense, out)
+        compare_clusters(*out.to_numpy()[:2], ref, kind + " dense")
+
+
+def test_server_matches_oracle_and_is_mix_independent(full):
+    cal, evs, refs, _ = full
+    with make_ctx(cal.noise, cal.gain, cal.bad, max_batch=4, n_streams=2) as ctx:
+        devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs]
+        hosts = [sc.Event(e.zs, e.fed_offset) for e in evs]
+        outs, tickets = [], []
+        for i in range(len(evs)):
+            ev = devs[i] if i % 2 == 0 else hosts[i]
+            o = ctx.output(*sc.safe_caps(hosts[i]), device=(i % 3 != 0))
+            outs.append(o)
+            tickets.append(ctx.submit(ev, o))
+        for t in tickets:
+            assert ctx.poll(t, -1) == sc.SC_OK
+        for i, (o, ref) in enumerate(zip(outs, refs)):
+            compare_clusters(*o.to_numpy()[:2], ref, f"served {i}")
+        # alone (one event in flight) gives the same bytes as inside the mix
+        o = ctx.output(*sc.safe_caps(hosts[5]))
+        t = ctx.submit(devs[5], o)
+        assert ctx.poll(t, -1) == sc.SC_OK
+        a, b = o.to_numpy(), outs[5].to_numpy()
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+        st = ctx.stats()
+        assert st["server_events"] == len(evs) + 1 and st["server_batches"] >= 2
+        assert ctx.poll(t, 0) == sc.SC_ERR_UNKNOWN_TICKET
+        assert ctx.poll(123456789, 0) == sc.SC_ERR_UNKNOWN_TICKET
+
+
+def test_server_budget_and_backpressure(full):
+    cal, evs, refs, _ = full
+    host = sc.Event(evs[0].zs, evs[0].fed_offset)
+    cap_cl, cap_adc = refs[0].cl.size, refs[0].adc.size
+    one = host.zs.size + 16 * cap_cl + 2 * cap_adc + 8 * 440 + 64
+    # budget below one event: refused outright
+    with make_ctx(cal.noise, cal.gain, cal.bad, hbm_budget=one // 2) as ctx:
+        o = ctx.output(cap_cl, cap_adc)
+        rc, _ = ctx.try_submit(host, o)
+        assert rc == sc.SC_ERR_BUDGET
+    # budget of ~1.5 events, one batch slot, queue of 1: submissions bounce with AGAIN while
+    # the queue is full, and every accepted event still completes exactly
+    with make_ctx(cal.noise, cal.gain, cal.bad, hbm_budget=int(one * 1.5), n_streams=1,
+                  max_batch=1, queue_depth=1) as ctx:
+        dev = host.to_device()
+        accepted, again = [], 0
+        for _ in range(2000):
+            o = ctx.output(cap_cl, cap_adc)
+            rc, t = ctx.try_submit(dev, o)
+            if rc == sc.SC_OK:
+                accepted.append((t, o))
+            else:
+                assert rc == sc.SC_ERR_AGAIN
+                again += 1
+            if again >= 3 and len(accepted) >= 3:
+                break
+        assert again >= 1
+        for t, o in accepted:
+            assert ctx.poll(t, -1) == sc.SC_OK
+            compare_clusters(*o.to_numpy()[:2], refs[0], "budgeted")
+
+
+def test_autotune_identical_and_cached(full, tmp_path):
+    cal, evs, refs, _ = full
+    cache = str(tmp_path / "tune.json")
+    with make_ctx(cal.noise, cal.gain, cal.bad, tune_cache=cache) as ctx:
+        devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs[:4]]
+        best = ctx.autotune(devs)
+        assert best["chunk_digis"] in (1024, 1536, 2048, 3072)
+        results, _, _, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs[:2]])
+        for r, ref in zip(results, refs[:2]):
+            compare_clusters(r[0], r[1], ref, "after autotune")
+    with make_ctx(cal.noise, cal.gain, cal.bad, tune_cache=cache) as ctx2:
+        t = ctx2.tuning
+        assert (t["chunk_digis"], t["waves_per_cu"], t["fed_major"]) == \
+            (best["chunk_digis"], best["waves_per_cu"], best["fed_major"])
