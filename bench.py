@@ -78,10 +78,16 @@ def main():
                     help="events of the batch the oracle processes for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-events", type=int, default=2000,
+                    help="events per arrival-rate point of the serving sweep")
     ap.add_argument("--tuning", default=None,
                     help="chunk_digis,waves_per_cu,fed_major,use_graph")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB 5 times (reference "
+                         "for the HBM byte counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -95,6 +101,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev_name = torch.cuda.get_device_name(0)
+    if args.copy_probe_mib:
+        a = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel(), "copies": 5}))
+        return
 
     # ---- workload: 64 full-detector events, occupancy log-uniform in [0.5%, 5%] -------------
     cfg = fedgen.CONFIGS[2]
@@ -210,6 +224,43 @@ def main():
         log(f"plain: {plain}")
         ctx1.close()
 
+    # ---- serving: Poisson arrivals of the occupancy mix {0.5,1.5,3,6}% -----------------------
+    serving = None
+    if not args.no_serve:
+        cfg3 = fedgen.CONFIGS[3]
+        cal3 = fedgen.make_calibration(cfg3)
+        pool = fedgen.make_events(cfg3, cal3, range(64), workers=args.workers)
+        ctx3 = sc.Context(cal3.noise, cal3.gain, cal3.bad, device=0, stream=stream,
+                          max_batch=64, n_streams=2)
+        ctx3.tuning = ctx.tuning
+        p_dev = [sc.Event(e.zs, e.fed_offset).to_device() for e in pool]
+        n_out = 256
+        p_out = [ctx3.output(*sc.safe_caps(p_dev[j % len(p_dev)])) for j in range(n_out)]
+        # batched capacity on this mix
+        for _ in range(3):
+            ctx3.process_events(p_dev, p_out[:len(p_dev)])
+        torch.cuda.synchronize()
+        tcap = time.perf_counter()
+        for _ in range(10):
+            ctx3.process_events(p_dev, p_out[:len(p_dev)])
+        torch.cuda.synchronize()
+        capacity = 10 * len(p_dev) / (time.perf_counter() - tcap)
+        points = []
+        for frac in (0.2, 0.4, 0.6, 0.8, 1.0, 1.2):
+            rc, lat, eps = ctx3.serve_replay(p_dev, p_out, args.serve_events, frac * capacity,
+                                             seed=int(frac * 1000))
+            points.append({"rate_frac": frac, "offered_events_per_s": frac * capacity,
+                           "achieved_events_per_s": eps,
+                           "latency_us_p50": float(np.percentile(lat, 50)),
+                           "latency_us_p99": float(np.percentile(lat, 99)), "status": rc})
+            log(f"serve {frac:.1f}: {points[-1]}")
+        serving = {"workload": f"Poisson arrivals, {args.serve_events} events per point, pool of "
+                               f"{len(pool)} full-detector events of the occupancy mix, device-"
+                               "resident inputs and outputs",
+                   "batched_capacity_events_per_s": capacity, "points": points,
+                   "server_batches": ctx3.stats()["server_batches"]}
+        ctx3.close()
+
     # ---- CPU baseline: the oracle on a bounded sample, one host core ------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -264,6 +315,7 @@ def main():
             "kernel": "fused_kernel",
         },
         "plain_path": plain,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

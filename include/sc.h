@@ -192,6 +192,16 @@ sc_status sc_submit(sc_ctx *ctx, const sc_event *ev, sc_clusters *out, uint64_t 
  * forgotten. */
 sc_status sc_poll(sc_ctx *ctx, uint64_t ticket, int64_t timeout_us);
 
+/* Open-loop load test of the server: submits n events at Poisson arrival times of mean rate
+ * rate_hz (exponential gaps from a generator seeded with seed), event i using ev[i % n_ev] and
+ * out[i % n_out]; an output slot is reused only once its previous event has completed. On return
+ * every event has completed; latency_us[i] (optional, n entries) receives completion time minus
+ * scheduled arrival time in microseconds (queueing included), *events_per_s (optional) the
+ * completed events per second over the run. Returns the worst event status. */
+sc_status sc_serve_replay(sc_ctx *ctx, const sc_event *ev, uint32_t n_ev, sc_clusters *out,
+                          uint32_t n_out, uint32_t n, double rate_hz, uint64_t seed,
+                          double *latency_us, double *events_per_s);
+
 /* Tuning of the fused kernel. sc_autotune times every candidate choice on the given events
  * (device or host), checks that all choices give identical clusters, keeps the fastest and, if
  * opt->tune_cache was set, stores it there. */

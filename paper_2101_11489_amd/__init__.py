@@ -34,8 +34,8 @@ CLUSTER_DTYPE = np.dtype([("channel", "<u4"), ("first", "<u2"), ("width", "<u2")
                           ("charge", "<u4"), ("barycenter", "<f4")])
 
 EXPORTED = ["sc_default_options", "sc_create", "sc_destroy", "sc_unpack", "sc_cluster",
-            "sc_process_events", "sc_submit", "sc_poll", "sc_get_tuning", "sc_set_tuning",
-            "sc_autotune", "sc_get_stats", "sc_last_error"]
+            "sc_process_events", "sc_submit", "sc_poll", "sc_serve_replay", "sc_get_tuning",
+            "sc_set_tuning", "sc_autotune", "sc_get_stats", "sc_last_error"]
 
 
 class ScError(RuntimeError):
@@ -103,6 +103,11 @@ def lib():
             "sc_submit": ([P, ctypes.POINTER(ScEvent), ctypes.POINTER(ScClusters),
                            ctypes.POINTER(ctypes.c_uint64)], st),
             "sc_poll": ([P, ctypes.c_uint64, ctypes.c_int64], st),
+            "sc_serve_replay": ([P, ctypes.POINTER(ScEvent), ctypes.c_uint32,
+                                 ctypes.POINTER(ScClusters), ctypes.c_uint32, ctypes.c_uint32,
+                                 ctypes.c_double, ctypes.c_uint64,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+                                st),
             "sc_get_tuning": ([P, ctypes.POINTER(ScTuning)], st),
             "sc_set_tuning": ([P, ctypes.POINTER(ScTuning)], st),
             "sc_autotune": ([P, ctypes.POINTER(ScEvent), ctypes.c_uint32,
@@ -357,6 +362,20 @@ class Context:
         if rc != SC_PENDING:
             self._pending.pop(ticket, None)
         return rc
+
+    def serve_replay(self, events, outs, n, rate_hz, seed=11489):
+        """Open-loop Poisson load on the server. Returns (status, latencies_us[n], events/s)."""
+        self._ready_for_server()
+        evs = (ScEvent * len(events))(*[e.c() for e in events])
+        cs = (ScClusters * len(outs))(*[o.cs for o in outs])
+        lat = (ctypes.c_double * n)()
+        eps = ctypes.c_double()
+        rc = lib().sc_serve_replay(self._h, evs, len(events), cs, len(outs), n, rate_hz, seed,
+                                   lat, ctypes.byref(eps))
+        for o, c in zip(outs, cs):
+            o.cs.n_cl, o.cs.n_adc = c.n_cl, c.n_adc
+        self._check(rc, (SC_OK, SC_MALFORMED, SC_ERR_OVERFLOW))
+        return rc, np.frombuffer(lat, dtype=np.float64).copy(), eps.value
 
     # -- tuning / stats --
     @property

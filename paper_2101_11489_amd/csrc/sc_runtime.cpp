@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdio>
 #include <cstring>
@@ -481,7 +482,7 @@ struct Req {
     std::vector<uint64_t> fo_copy;
     size_t bytes = 0;                     // budget reservation
     sc_status status = SC_PENDING;
-    std::chrono::steady_clock::time_point t_submit;
+    std::chrono::steady_clock::time_point t_submit, t_done;
 };
 }  // namespace
 
@@ -575,7 +576,8 @@ struct Server {
         return SC_OK;
     }
 
-    sc_status poll(uint64_t ticket, int64_t timeout_us) {
+    sc_status poll(uint64_t ticket, int64_t timeout_us,
+                   std::chrono::steady_clock::time_point* t_done = nullptr) {
         std::unique_lock<std::mutex> g(mu);
         auto it = tickets.find(ticket);
         if (it == tickets.end()) return SC_ERR_UNKNOWN_TICKET;
@@ -588,6 +590,7 @@ struct Server {
         }
         if (!done()) return SC_PENDING;
         tickets.erase(ticket);
+        if (t_done) *t_done = r->t_done;
         return r->status;
     }
 
@@ -632,11 +635,17 @@ struct Server {
         return true;
     }
 
-    void complete(std::vector<std::shared_ptr<Req>>& batch, sc_status forced) {
+    // Final status of every request of a batch (forced, or per event), completion time, and the
+    // budget it held; wakes pollers.
+    void complete(std::vector<std::shared_ptr<Req>>& batch, sc_status forced,
+                  const std::vector<sc_status>* per_event = nullptr) {
+        const auto now = std::chrono::steady_clock::now();
         std::lock_guard<std::mutex> g(mu);
-        for (auto& r : batch) {
+        for (size_t i = 0; i < batch.size(); ++i) {
+            auto& r = batch[i];
             reserved -= r->bytes;
-            if (forced != SC_OK) r->status = forced;
+            r->t_done = now;
+            r->status = forced != SC_OK ? forced : (per_event ? (*per_event)[i] : SC_OK);
         }
         batch.clear();
         cv_done.notify_all();
@@ -660,15 +669,11 @@ struct Server {
             for (uint32_t i = 0; i < n; ++i) outs[i] = *sl.batch[i]->out;
             std::vector<sc_status> sts(n, SC_OK);
             sc_status fs = finish_batch(c, sl.ws, sl.st, n, outs.data(), sts.data(), sl.s);
-            {
-                std::lock_guard<std::mutex> g(mu);
-                for (uint32_t i = 0; i < n; ++i) {
-                    sl.batch[i]->out->n_cl = outs[i].n_cl;
-                    sl.batch[i]->out->n_adc = outs[i].n_adc;
-                    sl.batch[i]->status = fs == SC_ERR_DEVICE ? SC_ERR_DEVICE : sts[i];
-                }
+            for (uint32_t i = 0; i < n; ++i) {
+                sl.batch[i]->out->n_cl = outs[i].n_cl;
+                sl.batch[i]->out->n_adc = outs[i].n_adc;
             }
-            complete(sl.batch, SC_OK);
+            complete(sl.batch, fs == SC_ERR_DEVICE ? SC_ERR_DEVICE : SC_OK, &sts);
             sl.busy = false;
         }
         return any;
@@ -932,6 +937,64 @@ sc_status sc_poll(sc_ctx* c, uint64_t ticket, int64_t timeout_us) {
     }
     if (!sv) return SC_ERR_UNKNOWN_TICKET;
     return sv->poll(ticket, timeout_us);
+}
+
+sc_status sc_serve_replay(sc_ctx* c, const sc_event* ev, uint32_t n_ev, sc_clusters* out,
+                          uint32_t n_out, uint32_t n, double rate_hz, uint64_t seed,
+                          double* latency_us, double* events_per_s) {
+    using clk = std::chrono::steady_clock;
+    if (!c) return SC_ERR_INVALID_ARG;
+    if (!ev || !out || n_ev == 0 || n_out == 0 || !(rate_hz > 0))
+        return fail(c, SC_ERR_INVALID_ARG, "replay arguments");
+    // SplitMix64 -> uniform (0,1] -> exponential gaps
+    uint64_t st = seed;
+    auto next_u = [&st]() {
+        uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return ((double)(z >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+    };
+    std::vector<uint64_t> slot_ticket(n_out, 0);
+    std::vector<int64_t> slot_event(n_out, -1);
+    std::vector<clk::time_point> t_arr(n);
+    std::vector<uint64_t> tickets(n, 0);
+    sc_status worst_st = SC_OK;
+    auto collect = [&](uint32_t j) -> sc_status {
+        if (!slot_ticket[j]) return SC_OK;
+        clk::time_point td;
+        sc_status s = c->server->poll(slot_ticket[j], -1, &td);
+        const int64_t i = slot_event[j];
+        if (latency_us && i >= 0)
+            latency_us[i] = std::chrono::duration<double, std::micro>(td - t_arr[i]).count();
+        slot_ticket[j] = 0;
+        worst_st = worst(worst_st, s);
+        return s;
+    };
+    const clk::time_point t0 = clk::now();
+    double t_rel = 0.0;
+    for (uint32_t i = 0; i < n; ++i) {
+        t_rel += -std::log(next_u()) / rate_hz;
+        t_arr[i] = t0 + std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(t_rel));
+        while (clk::now() < t_arr[i]) {
+        }
+        const uint32_t j = i % n_out;
+        if (collect(j) == SC_ERR_DEVICE) return SC_ERR_DEVICE;
+        uint64_t t = 0;
+        for (;;) {
+            sc_status s = sc_submit(c, &ev[i % n_ev], &out[j], &t);
+            if (s == SC_OK) break;
+            if (s != SC_ERR_AGAIN) return s;
+            std::this_thread::sleep_for(std::chrono::microseconds(5));
+        }
+        slot_ticket[j] = t;
+        slot_event[j] = i;
+    }
+    for (uint32_t j = 0; j < n_out; ++j)
+        if (collect(j) == SC_ERR_DEVICE) return SC_ERR_DEVICE;
+    const double secs = std::chrono::duration<double>(clk::now() - t0).count();
+    if (events_per_s) *events_per_s = n / secs;
+    return worst_st;
 }
 
 sc_status sc_get_tuning(const sc_ctx* c, sc_tuning* t) {

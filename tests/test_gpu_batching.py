@@ -260,3 +260,18 @@ def test_autotune_identical_and_cached(full, tmp_path):
         t = ctx2.tuning
         assert (t["chunk_digis"], t["waves_per_cu"], t["fed_major"]) == \
             (best["chunk_digis"], best["waves_per_cu"], best["fed_major"])
+
+
+def test_serve_replay_poisson(full):
+    """Open-loop Poisson arrivals through the server: every event completes with the oracle's
+    clusters, output slots are reused only after completion, latencies are positive."""
+    cal, evs, refs, _ = full
+    with make_ctx(cal.noise, cal.gain, cal.bad, max_batch=8, n_streams=2) as ctx:
+        devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs]
+        outs = [ctx.output(*sc.safe_caps(devs[j % len(devs)])) for j in range(2 * len(devs))]
+        rc, lat, eps = ctx.serve_replay(devs, outs, 300, rate_hz=20000.0, seed=3)
+        assert rc == sc.SC_OK
+        assert lat.shape == (300,) and (lat > 0).all()
+        assert eps > 0
+        for j, o in enumerate(outs):
+            compare_clusters(*o.to_numpy()[:2], refs[j % len(devs)], f"replay slot {j}")
