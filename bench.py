@@ -82,7 +82,7 @@ def main():
     ap.add_argument("--serve-events", type=int, default=2000,
                     help="events per arrival-rate point of the serving sweep")
     ap.add_argument("--tuning", default=None,
-                    help="chunk_digis,waves_per_cu,fed_major,use_graph")
+                    help="chunk_digis,tile_waves,tiles_per_cu,fed_major,use_graph")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -121,8 +121,9 @@ def main():
     stream = torch.cuda.Stream()
     ctx = sc.Context(cal.noise, cal.gain, cal.bad, device=0, stream=stream)
     if args.tuning:
-        c, w, f, g = (int(x) for x in args.tuning.split(","))
-        ctx.tuning = {"chunk_digis": c, "waves_per_cu": w, "fed_major": f, "use_graph": g}
+        c, w, t, f, g = (int(x) for x in args.tuning.split(","))
+        ctx.tuning = {"chunk_digis": c, "tile_waves": w, "tiles_per_cu": t, "fed_major": f,
+                      "use_graph": g}
     devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in events]
     outs = [ctx.output(*sc.safe_caps(d)) for d in devs]
     torch.cuda.synchronize()

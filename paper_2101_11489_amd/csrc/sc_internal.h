@@ -35,10 +35,10 @@ struct EventResult {
 
 // Device-resident calibration, derived once per context.
 struct DeviceCalib {
-    const uint2* strip;   // per strip: {noise FP32 bits, k_channel | k_seed << 8}
+    const float* noise;   // per strip: noise, or +inf when the strip is unusable
     const float* gain;    // per APV
     uint32_t n_fed;
-    float t_cluster;
+    float t_seed, t_channel, t_cluster;
 };
 
 struct FusedArgs {
@@ -53,18 +53,18 @@ struct FusedArgs {
 
 // Launch helpers (sc_kernels.hip). All enqueue on `stream` and return the launch error.
 hipError_t launch_derive_calib(const float* noise, const float* gain, const uint8_t* bad,
-                               uint32_t n_fed, float t_seed, float t_channel, uint2* strip_out,
-                               hipStream_t stream);
+                               uint32_t n_fed, float* noise_out, hipStream_t stream);
 hipError_t launch_reset(const FusedArgs& a, uint32_t n_fed, hipStream_t stream);
-hipError_t launch_fused(const FusedArgs& a, uint32_t chunk_digis, uint32_t grid,
-                        hipStream_t stream);
+hipError_t launch_fused(const FusedArgs& a, uint32_t tile_waves, uint32_t chunk_digis,
+                        uint32_t grid, hipStream_t stream);
 hipError_t launch_cluster_dense(const uint8_t* adc_dense, const FusedArgs& a,
-                                uint32_t chunk_digis, uint32_t grid, hipStream_t stream);
+                                uint32_t tile_waves, uint32_t chunk_digis, uint32_t grid,
+                                hipStream_t stream);
 hipError_t launch_unpack(const uint8_t* zs, const uint64_t* fed_off, uint32_t n_fed,
                          uint8_t* adc_dense, uint8_t* chan_status, EventResult* res,
                          hipStream_t stream);
-// Resident workgroups per compute unit for the fused kernel with this chunk size.
-int fused_blocks_per_cu(uint32_t chunk_digis, bool dense);
-bool chunk_digis_supported(uint32_t chunk_digis);
+// Resident workgroups per compute unit for a tile shape (waves per tile, digis per chunk).
+int fused_blocks_per_cu(uint32_t tile_waves, uint32_t chunk_digis, bool dense);
+bool tile_shape_supported(uint32_t tile_waves, uint32_t chunk_digis);
 
 }  // namespace sc

@@ -103,11 +103,11 @@ struct Workspace {
 };
 
 struct GraphKey {
-    uint32_t n_ev, chunk, grid, fed_major;
+    uint32_t n_ev, chunk, waves, grid, fed_major;
     uint64_t gen;
     bool operator<(const GraphKey& o) const {
-        return std::tie(n_ev, chunk, grid, fed_major, gen) <
-               std::tie(o.n_ev, o.chunk, o.grid, o.fed_major, o.gen);
+        return std::tie(n_ev, chunk, waves, grid, fed_major, gen) <
+               std::tie(o.n_ev, o.chunk, o.waves, o.grid, o.fed_major, o.gen);
     }
 };
 
@@ -123,7 +123,7 @@ struct sc_ctx {
     bool own_stream = false;
     uint32_t n_fed = 0;
     float t_seed = 3, t_channel = 2, t_cluster = 5;
-    uint2* d_strip = nullptr;
+    float* d_noise = nullptr;   // effective noise per strip (+inf: unusable)
     float* d_gain = nullptr;
     int n_cu = 0;
     std::string device_name;
@@ -165,8 +165,8 @@ sc_status device_fail(sc_ctx* c, hipError_t e, const char* where) {
     } while (0)
 
 uint32_t grid_for(const sc_ctx* c, uint32_t n_tiles, bool dense) {
-    const int occ = std::max(1, fused_blocks_per_cu(c->tuning.chunk_digis, dense));
-    const uint32_t per_cu = std::max<uint32_t>(1, std::min<uint32_t>(c->tuning.waves_per_cu, occ));
+    const int occ = std::max(1, fused_blocks_per_cu(c->tuning.tile_waves, c->tuning.chunk_digis, dense));
+    const uint32_t per_cu = std::max<uint32_t>(1, std::min<uint32_t>(c->tuning.tiles_per_cu, occ));
     const uint32_t g = per_cu * (uint32_t)std::max(1, c->n_cu);
     return std::max<uint32_t>(1, std::min<uint32_t>(g, n_tiles));
 }
@@ -319,9 +319,11 @@ FusedArgs fused_args(sc_ctx* c, Workspace& ws, uint32_t n) {
     a.res = ws.res.as<EventResult>();
     a.tile_state = ws.state.as<unsigned long long>();
     a.queue = ws.queue.as<uint32_t>();
-    a.cal.strip = c->d_strip;
+    a.cal.noise = c->d_noise;
     a.cal.gain = c->d_gain;
     a.cal.n_fed = c->n_fed;
+    a.cal.t_seed = c->t_seed;
+    a.cal.t_channel = c->t_channel;
     a.cal.t_cluster = c->t_cluster;
     a.n_ev = n;
     a.fed_major = c->tuning.fed_major;
@@ -337,7 +339,7 @@ hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bo
     if ((e = launch_reset(a, c->n_fed, s))) return e;
     if (timed && (e = hipEventRecord(c->ev0, s))) return e;
     const uint32_t grid = grid_for(c, n * c->n_fed, false);
-    if ((e = launch_fused(a, c->tuning.chunk_digis, grid, s))) return e;
+    if ((e = launch_fused(a, c->tuning.tile_waves, c->tuning.chunk_digis, grid, s))) return e;
     if (timed && (e = hipEventRecord(c->ev1, s))) return e;
     return hipMemcpyAsync(ws.h_res.p, ws.res.p, sizeof(EventResult) * n, hipMemcpyDeviceToHost, s);
 }
@@ -345,7 +347,8 @@ hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bo
 // Replays (capturing on first use) the batched launch as a hipGraph.
 hipError_t enqueue_batch_graph(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s) {
     const uint32_t grid = grid_for(c, n * c->n_fed, false);
-    GraphKey k{n, c->tuning.chunk_digis, grid, c->tuning.fed_major, ws.generation};
+    GraphKey k{n, c->tuning.chunk_digis, c->tuning.tile_waves, grid, c->tuning.fed_major,
+               ws.generation};
     auto it = c->graphs.find(k);
     hipError_t e;
     if (it == c->graphs.end()) {
@@ -416,7 +419,8 @@ sc_status run_batch(sc_ctx* c, const sc_event* ev, uint32_t n, sc_clusters* out,
     return finish_batch(c, c->ws, st, n, out, ev_status, c->stream);
 }
 
-// ---- autotuner cache (tiny JSON: {"<device>/<n_fed>": [chunk, waves, fed_major, graph]}) ----
+// ---- autotuner cache (tiny JSON: {"<device>/<n_fed>": [chunk, tile waves, tiles/CU,
+//      fed_major, graph]}) ----
 std::string tune_key(const sc_ctx* c) {
     return c->device_name + "/" + std::to_string(c->n_fed);
 }
@@ -433,10 +437,10 @@ bool load_tuning(sc_ctx* c) {
     if (p == std::string::npos) return false;
     p = txt.find('[', p);
     if (p == std::string::npos) return false;
-    unsigned a = 0, b = 0, d = 0, g = 0;
-    if (std::sscanf(txt.c_str() + p, "[%u,%u,%u,%u]", &a, &b, &d, &g) != 4) return false;
-    if (!chunk_digis_supported(a) || b < 1 || b > 32) return false;
-    c->tuning = sc_tuning{a, b, d ? 1u : 0u, g ? 1u : 0u};
+    unsigned a = 0, w = 0, b = 0, d = 0, g = 0;
+    if (std::sscanf(txt.c_str() + p, "[%u,%u,%u,%u,%u]", &a, &w, &b, &d, &g) != 5) return false;
+    if (!tile_shape_supported(w, a) || b < 1 || b > 32) return false;
+    c->tuning = sc_tuning{a, w, b, d ? 1u : 0u, g ? 1u : 0u};
     return true;
 }
 
@@ -456,8 +460,9 @@ void save_tuning(const sc_ctx* c) {
         }
     }
     char buf[96];
-    std::snprintf(buf, sizeof buf, "[%u,%u,%u,%u]", c->tuning.chunk_digis, c->tuning.waves_per_cu,
-                  c->tuning.fed_major, c->tuning.use_graph);
+    std::snprintf(buf, sizeof buf, "[%u,%u,%u,%u,%u]", c->tuning.chunk_digis,
+                  c->tuning.tile_waves, c->tuning.tiles_per_cu, c->tuning.fed_major,
+                  c->tuning.use_graph);
     entries[tune_key(c)] = buf;
     std::ofstream f(c->tune_cache, std::ios::trunc);
     f << "{\n";
@@ -744,7 +749,7 @@ sc_status sc_create(const sc_calib* cal, const sc_options* opt_in, sc_ctx** out)
         return fail(nullptr, SC_ERR_DEVICE, "hipGetDeviceProperties");
     c->n_cu = prop.multiProcessorCount;
     c->device_name = prop.gcnArchName;
-    c->tuning = sc_tuning{2048, 32, 1, 1};
+    c->tuning = sc_tuning{1536, 1, 32, 1, 1};
     load_tuning(c.get());
     if (opt.stream) {
         c->stream = static_cast<hipStream_t>(opt.stream);
@@ -757,20 +762,19 @@ sc_status sc_create(const sc_calib* cal, const sc_options* opt_in, sc_ctx** out)
         return fail(nullptr, SC_ERR_DEVICE, "hipEventCreate");
     const size_t n_strips = (size_t)cal->n_fed * kChannelsPerFed * kStripsPerChannel;
     const size_t n_apv = n_strips / kStripsPerApv;
-    float* d_noise = nullptr;
+    float* d_noise_raw = nullptr;
     uint8_t* d_bad = nullptr;
-    hipError_t e = hipMalloc(&c->d_strip, sizeof(uint2) * n_strips);
+    hipError_t e = hipMalloc(&c->d_noise, sizeof(float) * n_strips);
     if (e == hipSuccess) e = hipMalloc(&c->d_gain, sizeof(float) * n_apv);
-    if (e == hipSuccess) e = hipMalloc(&d_noise, sizeof(float) * n_strips);
+    if (e == hipSuccess) e = hipMalloc(&d_noise_raw, sizeof(float) * n_strips);
     if (e == hipSuccess) e = hipMalloc(&d_bad, n_strips);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_noise, cal->noise, sizeof(float) * n_strips, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_noise_raw, cal->noise, sizeof(float) * n_strips, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->d_gain, cal->gain, sizeof(float) * n_apv, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d_bad, cal->bad, n_strips, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
-        e = launch_derive_calib(d_noise, c->d_gain, d_bad, cal->n_fed, cal->t_seed,
-                                cal->t_channel, c->d_strip, c->stream);
+        e = launch_derive_calib(d_noise_raw, c->d_gain, d_bad, cal->n_fed, c->d_noise, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (d_noise) (void)hipFree(d_noise);
+    if (d_noise_raw) (void)hipFree(d_noise_raw);
     if (d_bad) (void)hipFree(d_bad);
     if (e == hipSuccess) e = c->ws.ensure_batch(64, c->n_fed);
     if (e != hipSuccess) {
@@ -789,7 +793,7 @@ void sc_destroy(sc_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->ws.release();
-    if (c->d_strip) (void)hipFree(c->d_strip);
+    if (c->d_noise) (void)hipFree(c->d_noise);
     if (c->d_gain) (void)hipFree(c->d_gain);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -878,7 +882,8 @@ sc_status sc_cluster(sc_ctx* c, const uint8_t* adc_dense, sc_mem in_mem, sc_clus
     FusedArgs a = fused_args(c, ws, 1);
     SC_HIP(c, launch_reset(a, c->n_fed, c->stream));
     SC_HIP(c, hipEventRecord(c->ev0, c->stream));
-    SC_HIP(c, launch_cluster_dense(d_in, a, c->tuning.chunk_digis, grid_for(c, c->n_fed, true), c->stream));
+    SC_HIP(c, launch_cluster_dense(d_in, a, c->tuning.tile_waves, c->tuning.chunk_digis,
+                                   grid_for(c, c->n_fed, true), c->stream));
     SC_HIP(c, hipEventRecord(c->ev1, c->stream));
     SC_HIP(c, hipMemcpyAsync(ws.h_res.p, ws.res.p, sizeof(EventResult), hipMemcpyDeviceToHost, c->stream));
     SC_HIP(c, hipStreamSynchronize(c->stream));
@@ -1005,8 +1010,10 @@ sc_status sc_get_tuning(const sc_ctx* c, sc_tuning* t) {
 
 sc_status sc_set_tuning(sc_ctx* c, const sc_tuning* t) {
     if (!c || !t) return SC_ERR_INVALID_ARG;
-    if (!chunk_digis_supported(t->chunk_digis) || t->waves_per_cu < 1 || t->waves_per_cu > 32)
-        return fail(c, SC_ERR_INVALID_ARG, "unsupported tuning");
+    if (!tile_shape_supported(t->tile_waves, t->chunk_digis) || t->tiles_per_cu < 1 ||
+        t->tiles_per_cu > 32)
+        return fail(c, SC_ERR_INVALID_ARG,
+                    "unsupported tuning (tile_waves must be 1; chunk_digis 1024, 1536 or 2048)");
     c->tuning = *t;
     c->tuning.fed_major = t->fed_major ? 1 : 0;
     c->tuning.use_graph = t->use_graph ? 1 : 0;
@@ -1052,12 +1059,9 @@ sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best
     }
     const sc_tuning saved = c->tuning;
     std::vector<sc_tuning> cands;
-    for (uint32_t d : {1024u, 1536u, 2048u, 3072u})
-        for (uint32_t fm : {0u, 1u}) {
-            const int occ = fused_blocks_per_cu(d, false);
-            for (uint32_t w : {(uint32_t)occ, (uint32_t)std::max(1, occ / 2)})
-                cands.push_back(sc_tuning{d, w, fm, 0});
-        }
+    for (uint32_t d : {1024u, 1536u, 2048u})
+        for (uint32_t fm : {0u, 1u})
+            if (tile_shape_supported(1, d)) cands.push_back(sc_tuning{d, 1, 32, fm, 0});
     std::vector<uint8_t> ref_cl, ref_adc, cur_cl, cur_adc;
     double best_ms = 1e30;
     sc_tuning best_t = saved;

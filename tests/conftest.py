@@ -19,3 +19,11 @@ def _oracle_built():
     if not os.path.exists(oracle.LIB) or os.path.getmtime(oracle.LIB) < os.path.getmtime(oracle.SRC):
         oracle.build(force=True)
     yield
+
+
+def pytest_runtest_logstart(nodeid, location):
+    # one line per test as it starts, so a long GPU run shows where it is
+    import sys
+    import time
+    sys.stderr.write(f"[{time.strftime('%H:%M:%S')}] start {nodeid}\n")
+    sys.stderr.flush()
