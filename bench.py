@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="chunk_digis,tile_waves,tiles_per_cu,fed_major,use_graph")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the batched launch as a graph (kernel time is then not measured)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB 5 times (reference "
@@ -130,6 +132,11 @@ def main():
     if args.autotune:
         t = ctx.autotune(devs)
         log(f"autotuned: {t}")
+    # The timed launches run eagerly: the library then records its HIP events on the launch
+    # stream right around the fused kernel, which gives the kernel's own duration per launch.
+    # (A captured graph is replayed as a whole; its launch overhead is negligible at this size.)
+    if not args.graph:
+        ctx.tuning = {"use_graph": 0}
 
     # ---- warm-up, then a sampled parity check at full size ---------------------------------
     for _ in range(args.warmup):

@@ -138,8 +138,8 @@ typedef struct {
 
 /* Performance-relevant choices of the fused kernel (found by sc_autotune). */
 typedef struct {
-    uint32_t chunk_digis;    /* digis a tile holds in LDS per pass: 1024, 1536 or 2048 */
-    uint32_t tile_waves;     /* wavefronts per tile (workgroup); only 1 is enabled */
+    uint32_t chunk_digis;    /* digis a tile holds in LDS per pass: 1024, 2048, 3072, 4096 */
+    uint32_t tile_waves;     /* wavefronts per tile (workgroup); must be 1 */
     uint32_t tiles_per_cu;   /* cap on resident tiles per compute unit (persistent grid), 1..32 */
     uint32_t fed_major;      /* 1: tiles ordered FED-major (calibration reuse), 0: event-major */
     uint32_t use_graph;      /* 1: replay the batched launch as a captured hipGraph */

@@ -167,7 +167,7 @@ def _edge_event(kind):
 
 @pytest.mark.parametrize("kind", ["all_empty", "zero_length_feds", "full_fed", "alternating_fed",
                                   "multichunk_fits_stage", "garbage"])
-@pytest.mark.parametrize("shape", [(1024, 1), (1536, 1), (2048, 1)])
+@pytest.mark.parametrize("shape", [(1024, 1), (2048, 1), (4096, 1)])
 def test_edge_cases(kind, shape):
     zs, fo, noise, gain, bad = _edge_event(kind)
     ref = oracle.process_event(zs, fo, noise, gain, bad)
@@ -252,7 +252,7 @@ def test_autotune_identical_and_cached(full, tmp_path):
     with make_ctx(cal.noise, cal.gain, cal.bad, tune_cache=cache) as ctx:
         devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs[:4]]
         best = ctx.autotune(devs)
-        assert best["chunk_digis"] in (1024, 1536, 2048) and best["tile_waves"] == 1
+        assert best["chunk_digis"] in (1024, 2048, 3072, 4096) and best["tile_waves"] == 1
         results, _, _, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs[:2]])
         for r, ref in zip(results, refs[:2]):
             compare_clusters(r[0], r[1], ref, "after autotune")

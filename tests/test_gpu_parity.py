@@ -22,9 +22,6 @@ if not torch.cuda.is_available():
 import paper_2101_11489_amd as sc  # noqa: E402
 from gpu_common import bary_bit_exact, compare_clusters, make_ctx, run_fused  # noqa: E402
 
-MULTIWAVE_OFF = ("multi-wave tiles are switched off: their first GPU run hung (a lane-split tile "
-                 "loop, since removed); the fixed build has not run on the GPU yet")
-
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 HAND = json.load(open(os.path.join(GOLD, "hand_channels.json")))["cases"]
 UNPACK = json.load(open(os.path.join(GOLD, "unpack_cases.json")))["cases"]
@@ -122,14 +119,12 @@ def test_plain_path_unpack_then_cluster(cfg0):
     compare_clusters(cl, adc, ref, "plain")
 
 
-@pytest.mark.parametrize("chunk", [1024, 1536, 2048])
-@pytest.mark.parametrize("waves", [1, pytest.param(2, marks=pytest.mark.skip(reason=MULTIWAVE_OFF)),
-                                   pytest.param(4, marks=pytest.mark.skip(reason=MULTIWAVE_OFF))])
+@pytest.mark.parametrize("chunk", [1024, 2048, 3072, 4096])
 @pytest.mark.parametrize("fed_major", [0, 1])
-def test_tuning_choices_identical(cfg0, chunk, waves, fed_major):
+def test_tuning_choices_identical(cfg0, chunk, fed_major):
     cfg, cal, evs, ctx = cfg0
     refs = [oracle.process_event(e.zs, e.fed_offset, cal.noise, cal.gain, cal.bad) for e in evs[:3]]
-    ctx.tuning = {"chunk_digis": chunk, "tile_waves": waves, "fed_major": fed_major,
+    ctx.tuning = {"chunk_digis": chunk, "tile_waves": 1, "fed_major": fed_major,
                   "use_graph": 0}
     try:
         results, rc, _, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs[:3]])
@@ -141,12 +136,12 @@ def test_tuning_choices_identical(cfg0, chunk, waves, fed_major):
         ctx.cluster(dense, out)
         compare_clusters(*out.to_numpy()[:2], refs[0], f"dense chunk {chunk}")
     finally:
-        ctx.tuning = {"chunk_digis": 1536, "tile_waves": 1, "fed_major": 1, "use_graph": 1}
+        ctx.tuning = {"chunk_digis": 2048, "tile_waves": 1, "fed_major": 1, "use_graph": 1}
 
 
-def test_multiwave_tiles_are_refused(cfg0):
+def test_unsupported_tile_shapes_are_refused(cfg0):
     cfg, cal, evs, ctx = cfg0
-    for w in (2, 4):
+    for t in ({"tile_waves": 2}, {"tile_waves": 4}, {"chunk_digis": 1536}, {"chunk_digis": 512}):
         with pytest.raises(sc.ScError):
-            ctx.tuning = {"tile_waves": w}
-    assert ctx.tuning["tile_waves"] == 1
+            ctx.tuning = t
+    assert ctx.tuning["tile_waves"] == 1 and ctx.tuning["chunk_digis"] == 2048
