@@ -209,24 +209,27 @@ __device__ WalkResult walk_fed(TileSmem<D>& sm, const uint8_t* g, uint32_t L, co
     uint32_t delta = stage_bytes(sm, g, fits ? L : cap, gains);
     uint32_t pos = 0, bad_from = kNch;
     if (fits) {
-        // the whole FED is staged; lane k (mod 64) keeps channel k's record position and length
+        // the whole FED is staged; lane k (mod 64) keeps channel k's record position and length.
+        // Branch-free steps: after the first record that does not fit, pos stays put and the
+        // remaining steps only re-read (inside the stage) without effect.
+        constexpr uint32_t omax = TileSmem<D>::kStageBytes - 2;
         uint32_t vpos0 = 0, vpos1 = 0, vlen0 = 0, vlen1 = 0;
-        for (uint32_t k = 0; k < (uint32_t)kNch; ++k) {
-            if (pos + 2 > L) { bad_from = k; break; }
-            const uint32_t o = pos + delta;
+        auto step = [&](uint32_t k, uint32_t& vpos, uint32_t& vlen) {
+            uint32_t o = pos + delta;
+            o = o < omax ? o : omax;
             const uint32_t P =
                 uni((uint32_t)sm.u.stage[o] | ((uint32_t)sm.u.stage[o + 1] << 8));
-            if (pos + 2 + P > L) { bad_from = k; break; }
+            const bool ok = bad_from == (uint32_t)kNch && pos + 2 <= L && pos + 2 + P <= L;
+            bad_from = (bad_from == (uint32_t)kNch && !ok) ? k : bad_from;
             const bool mine = lane() == (k & 63u);
-            if (k < 64) {
-                vpos0 = mine ? pos + 2 : vpos0;
-                vlen0 = mine ? P : vlen0;
-            } else {
-                vpos1 = mine ? pos + 2 : vpos1;
-                vlen1 = mine ? P : vlen1;
-            }
-            pos += 2 + P;
-        }
+            vpos = mine ? pos + 2 : vpos;
+            vlen = mine ? P : vlen;
+            pos = ok ? pos + 2 + P : pos;
+        };
+#pragma unroll 8
+        for (uint32_t k = 0; k < 64u; ++k) step(k, vpos0, vlen0);
+#pragma unroll 8
+        for (uint32_t k = 64; k < (uint32_t)kNch; ++k) step(k, vpos1, vlen1);
         sm.ch_pos[lane()] = vpos0;
         sm.ch_len[lane()] = (uint16_t)vlen0;
         sm.ch_pos[64 + lane()] = vpos1;   // entries 96..127 are never read
@@ -798,37 +801,42 @@ __device__ void dense_tile(const FusedArgs& A, TileSmem<D>& sm, const uint8_t* d
 
 // ---- kernels --------------------------------------------------------------------------------
 // The next tile of the queue. Every lane executes the atomic, adding 1 from lane 0 and 0 from
-// the others (no lane test); lane 0's old value is the tile.
+// the others (no lane test); lane 0's old value is the tile. Tiles are taken in a global order
+// (FED-major or event-major) in which a tile's look-back predecessors come before it, so the
+// lowest unfinished tile of an event has always been taken and every look-back ends, whatever
+// part of the grid is resident.
 __device__ __forceinline__ uint32_t next_tile(uint32_t* queue) {
     return uni(atomicAdd(queue, lane() == 0u ? 1u : 0u));
+}
+
+// Runs tile(e, f) for every tile of an n_ev x n_fed launch.
+template <class TileFn>
+__device__ __forceinline__ void run_tiles(uint32_t* queue, uint32_t n_ev, uint32_t n_fed,
+                                          uint32_t fed_major, TileFn tile) {
+    const uint32_t n_tiles = n_ev * n_fed;
+    for (;;) {
+        const uint32_t t = next_tile(queue);
+        if (t >= n_tiles) break;
+        uint32_t e, f;
+        if (fed_major) { f = t / n_ev; e = t - f * n_ev; }
+        else           { e = t / n_fed; f = t - e * n_fed; }
+        tile(e, f);
+        tile_sync();   // the tile ends here for every lane (a convergent point)
+    }
 }
 
 template <int D>
 __global__ __launch_bounds__(kWave) void fused_kernel(FusedArgs A) {
     __shared__ TileSmem<D> sm;
-    const uint32_t n_fed = A.cal.n_fed;
-    const uint32_t n_tiles = A.n_ev * n_fed;
-    for (;;) {
-        const uint32_t t = next_tile(A.queue);
-        if (t >= n_tiles) break;
-        uint32_t e, f;
-        if (A.fed_major) { e = t % A.n_ev; f = t / A.n_ev; }
-        else             { e = t / n_fed; f = t % n_fed; }
-        zs_tile<D>(A, sm, e, f);
-        tile_sync();   // the tile ends here for every lane (a convergent point)
-    }
+    run_tiles(A.queue, A.n_ev, A.cal.n_fed, A.fed_major,
+              [&](uint32_t e, uint32_t f) { zs_tile<D>(A, sm, e, f); });
 }
 
 template <int D>
 __global__ __launch_bounds__(kWave) void cluster_dense_kernel(const uint8_t* dense, FusedArgs A) {
     __shared__ TileSmem<D> sm;
-    const uint32_t n_tiles = A.cal.n_fed;
-    for (;;) {
-        const uint32_t t = next_tile(A.queue);
-        if (t >= n_tiles) break;
-        dense_tile<D>(A, sm, dense, t);
-        tile_sync();   // the tile ends here for every lane (a convergent point)
-    }
+    run_tiles(A.queue, 1u, A.cal.n_fed, 1u,
+              [&](uint32_t, uint32_t f) { dense_tile<D>(A, sm, dense, f); });
 }
 
 // ZS -> dense rows, one FED per single-wave workgroup.
