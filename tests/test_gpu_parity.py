@@ -141,7 +141,8 @@ def test_tuning_choices_identical(cfg0, chunk, fed_major):
 
 def test_unsupported_tile_shapes_are_refused(cfg0):
     cfg, cal, evs, ctx = cfg0
-    for t in ({"tile_waves": 2}, {"tile_waves": 4}, {"chunk_digis": 1536}, {"chunk_digis": 512}):
+    before = ctx.tuning
+    for t in ({"tile_waves": 3}, {"tile_waves": 8}, {"chunk_digis": 1536}, {"chunk_digis": 512}):
         with pytest.raises(sc.ScError):
             ctx.tuning = t
-    assert ctx.tuning["tile_waves"] == 1 and ctx.tuning["chunk_digis"] == 2048
+    assert ctx.tuning == before
