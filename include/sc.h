@@ -138,8 +138,8 @@ typedef struct {
 
 /* Performance-relevant choices of the fused kernel (found by sc_autotune). */
 typedef struct {
-    uint32_t chunk_digis;    /* digis a tile holds in LDS per pass: 1024, 2048, 3072, 4096 */
-    uint32_t tile_waves;     /* wavefronts per tile (workgroup); must be 1 */
+    uint32_t chunk_digis;    /* digis a tile holds in LDS per pass: 2048, 3072, 4096; 1024 with 1 wave */
+    uint32_t tile_waves;     /* wavefronts per tile: 1, 2 or 4 (each takes 96/W channels) */
     uint32_t tiles_per_cu;   /* cap on resident tiles per compute unit (persistent grid), 1..32 */
     uint32_t fed_major;      /* 1: tiles ordered FED-major (calibration reuse), 0: event-major */
     uint32_t use_graph;      /* 1: replay the batched launch as a captured hipGraph */

@@ -5,20 +5,21 @@
 // over strips, then cluster forming over seeds. §3 (Optimization): several events in flight.
 //
 // MI355X design (not the paper's CUDA design):
-//  * one wavefront owns one (event, FED) tile at a time; a persistent grid pulls tiles from an
-//    atomic queue, FED-major (the events of one FED back to back, so its calibration is reused
-//    from cache) or event-major;
-//  * the FED's bytes and gains are staged into LDS with all 16-byte loads in flight at once; the
-//    96 length fields are walked in LDS (the channel map the paper builds on the CPU); one lane
-//    per channel validates and expands the records into a compact digi list in LDS;
+//  * a workgroup of W wavefronts owns one (event, FED) tile at a time; a persistent grid pulls
+//    tiles from an atomic queue, FED-major (the events of one FED back to back, so its
+//    calibration is reused from cache) or event-major;
+//  * the FED's bytes and gains are staged into LDS with all 16-byte loads in flight at once; wave
+//    0 walks the 96 length fields in LDS (the channel map the paper builds on the CPU); then each
+//    wave takes a group of 96/W channels on its own: one lane per channel validates and expands
+//    the records into the wave's digi list in LDS;
 //  * cluster forming runs digi-parallel, 64 digis per step, with the calibration gathers of
 //    several steps in flight: the active/seed tests use one FP32 effective noise per strip
 //    (+inf for unusable strips, which never passes ADC > T*noise); a run is a chain of active
 //    digis on adjacent strips, and the sequential noise sum of each run is carried from lane to
 //    lane with DPP lane shifts, one strip position per iteration, so no lane walks memory;
-//  * the tile publishes its counts and looks back over earlier FEDs of its event, 64 FEDs per
-//    load (decoupled look-back), for its output offsets; records are written by the lane of each
-//    cluster's last strip, member ADCs one lane per digi.
+//  * each channel group publishes its counts and looks back over the earlier groups of its event,
+//    64 per load (decoupled look-back), for its output offsets; records are written by the lane
+//    of each cluster's last strip, member ADCs (gain-corrected here) one lane per digi.
 // No MFMA: nothing here is a dense contraction.
 
 #include <type_traits>
@@ -103,7 +104,8 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // may thread two such branches across a loop back edge; the loop then splits into an inner loop
 // for some lanes of the wavefront and an outer one for the others, which a SIMD machine runs as
 // a deadlock. Work done "by one lane" is instead done by every lane with identical values, lane
-// tests only select values, and every tile ends at a barrier.
+// tests only select values, and every tile ends at a barrier. Branches on the wave index are
+// uniform per wavefront; workgroup barriers sit only where every wave passes (tile level).
 
 // ---- look-back words: flag(2) | n_cl(31) | n_adc(31) -------------------------------------
 constexpr uint64_t kFlagAgg = 1, kFlagIncl = 2;
@@ -112,89 +114,96 @@ __device__ __forceinline__ unsigned long long pack_state(uint64_t flag, uint32_t
     return (flag << 62) | ((uint64_t)(ncl & 0x7fffffffu) << 31) | (uint64_t)(nadc & 0x7fffffffu);
 }
 
-// Digi word in the list. While building: adc(8) | strip(8) | channel-in-FED(7). After forming:
-// run position(8) | strip(8) | channel(7) | active | seed | continues-previous | accepted (the
-// accepted bit on the first digi of an accepted run).
+// Digi word in the list: adc(8) | strip(8) | channel-in-FED(7), and after forming the flags
+// active | seed | continues-previous | accepted (the accepted bit on the first digi of an
+// accepted run).
 constexpr uint32_t kActBit = 1u << 23, kSeedBit = 1u << 24, kContBit = 1u << 25,
                    kAccBit = 1u << 26;
 constexpr uint32_t kNoKey = 0xffffffffu;
-__device__ __forceinline__ uint32_t d_low(uint32_t d) { return d & 255u; }   // adc, or run pos
+__device__ __forceinline__ uint32_t d_adc(uint32_t d) { return d & 255u; }
 __device__ __forceinline__ uint32_t d_strip(uint32_t d) { return (d >> 8) & 255u; }
 __device__ __forceinline__ uint32_t d_ch(uint32_t d) { return (d >> 16) & 127u; }
 __device__ __forceinline__ uint32_t d_pos(uint32_t d) { return (d >> 8) & 0x7fffu; }
 
-template <int D>
+template <int W, int DW>
 struct TileSmem {
-    // FED bytes while the digi list is built; the gain-corrected ADCs (u16 per digi) afterwards
-    static constexpr int kStageBytes = (2 * D > 8192) ? 2 * D : 8192;
+    static constexpr int kStageBytes = 8192;
     static constexpr int kStageData = kStageBytes - 16;   // FED bytes that fit (alignment slack)
-    union U {
-        uint8_t stage[kStageBytes];
-        uint16_t c[D];
-    };
-    alignas(16) U u;
-    uint32_t digi[D];
-    alignas(16) float gain[2 * kNch];   // the FED's APV gains
-    uint32_t ch_pos[2 * kWave];         // 96 used; 128 so that two full-wave stores fit
-    uint32_t ch_base[kNch + 1];
+    alignas(16) uint8_t stage[kStageBytes];              // the FED's bytes
+    uint32_t digi[W * DW];                               // wave w: [w*DW, (w+1)*DW)
+    alignas(16) float gain[2 * kNch];                    // the FED's APV gains
+    uint32_t ch_pos[2 * kWave];   // 96 used; 128 so that two full-wave stores fit
     uint16_t ch_len[2 * kWave];
+    uint32_t ch_base[kNch + W];   // channel c of wave w at index c + w: digi offset in the group
     uint8_t ch_st[kNch];
-    uint8_t chunk_first[kNch + 1];
+    uint8_t chunk_first[W][kNch + 1];
+    uint32_t walk[4];             // bad_from, trailing, delta (from wave 0)
 };
 
+// Workgroup barrier (every wave of the tile passes it); a no-op for single-wave tiles.
 __device__ __forceinline__ void tile_sync() { __syncthreads(); }
+// Orders this wavefront's LDS accesses (lanes of one wave see each other's earlier stores).
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
-// The FED's 192 APV gains into LDS (lanes past the 48th repeat the last vector).
-template <int D>
+// Index of the calling wave in the tile, as a uniform (scalar) value.
+template <int W>
+__device__ __forceinline__ uint32_t wave_index() {
+    if constexpr (W == 1) return 0u;
+    else return uni(threadIdx.x >> 6);
+}
+
+// The FED's 192 APV gains as 48 16-byte vectors (lanes past the 48th repeat the last one).
 __device__ __forceinline__ u32x4 load_gain_vec(const float* gains) {
     const uint32_t i = lane() < kGainVecs ? lane() : kGainVecs - 1u;
     return gc(reinterpret_cast<const u32x4*>(gains))[i];
 }
-template <int D>
-__device__ __forceinline__ void store_gain_vec(TileSmem<D>& sm, u32x4 v) {
+template <int W, int DW>
+__device__ __forceinline__ void store_gain_vec(TileSmem<W, DW>& sm, u32x4 v) {
     const uint32_t i = lane() < kGainVecs ? lane() : kGainVecs - 1u;
     reinterpret_cast<u32x4*>(sm.gain)[i] = v;
 }
 
 // ---- staging -----------------------------------------------------------------------------
 // Copy n bytes at gsrc into the stage so that gsrc[i] lands at stage[delta + i]; returns delta.
-// Loads are aligned 16-byte pieces, all issued before the first is stored; each piece holds at
-// least one byte of [gsrc, gsrc+n), so it lies inside the 4 KiB page of a byte of the buffer.
-// With gains != nullptr the FED's APV gains are loaded in the same batch.
-template <int D>
-__device__ __forceinline__ uint32_t stage_bytes(TileSmem<D>& sm, const uint8_t* gsrc, uint32_t n,
+// NT threads take part (thread index t): all waves of the tile, or wave 0 alone. Loads are
+// aligned 16-byte pieces, all issued before the first is stored; each piece holds at least one
+// byte of [gsrc, gsrc+n), so it lies inside the 4 KiB page of a byte of the buffer. With gains
+// != nullptr the FED's APV gains are loaded in the same batch (by wave 0).
+template <int NT, int W, int DW>
+__device__ __forceinline__ uint32_t stage_bytes(TileSmem<W, DW>& sm, uint32_t t,
+                                                const uint8_t* gsrc, uint32_t n,
                                                 const float* gains) {
-    constexpr int K = TileSmem<D>::kStageBytes / (16 * kWave);
+    constexpr int K = TileSmem<W, DW>::kStageBytes / (16 * NT);
     const uintptr_t a = reinterpret_cast<uintptr_t>(gsrc);
     const uintptr_t a0 = a & ~uintptr_t(15);
     const uint32_t delta = (uint32_t)(a - a0);
     const uint32_t nchunks = n ? (delta + n + 15u) >> 4 : 0u;
     gconst<u32x4>* s4 = gc(reinterpret_cast<const u32x4*>(a0));
-    u32x4* d4 = reinterpret_cast<u32x4*>(sm.u.stage);
+    u32x4* d4 = reinterpret_cast<u32x4*>(sm.stage);
+    const bool lead = wave_index<W>() == 0u;
     u32x4 gv = {0u, 0u, 0u, 0u};
-    if (gains) gv = load_gain_vec<D>(gains);
+    if (gains && lead) gv = load_gain_vec(gains);
     if (nchunks) {
-        // every lane loads K pieces (indices past the end repeat the last piece), then stores
+        // every thread loads K pieces (indices past the end repeat the last piece), then stores
         // the ones that exist
         const uint32_t last = nchunks - 1u;
         u32x4 r[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const uint32_t c = lane() + (uint32_t)(k * kWave);
+            const uint32_t c = t + (uint32_t)(k * NT);
             r[k] = s4[c < last ? c : last];
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const uint32_t c = lane() + (uint32_t)(k * kWave);
+            const uint32_t c = t + (uint32_t)(k * NT);
             if (c < nchunks) d4[c] = r[k];
         }
     }
-    if (gains) store_gain_vec(sm, gv);
-    tile_sync();
+    if (gains && lead) store_gain_vec(sm, gv);
     return delta;
 }
 
-// ---- channel map: the 96 length fields (uniform walk) --------------------------------------
+// ---- channel map: the 96 length fields (uniform walk by wave 0) ----------------------------
 struct WalkResult {
     uint32_t bad_from;   // first channel failing the record-in-FED rule (96: none)
     uint32_t trailing;   // 1 if bytes follow the 96th record
@@ -202,71 +211,90 @@ struct WalkResult {
     uint32_t delta;      // stage offset of FED byte 0 (when fits)
 };
 
-template <int D>
-__device__ WalkResult walk_fed(TileSmem<D>& sm, const uint8_t* g, uint32_t L, const float* gains) {
-    constexpr uint32_t cap = TileSmem<D>::kStageData;
+// Stages the FED (and its gains) and walks its length fields; the channel positions and lengths
+// go to LDS. Every wave of the tile calls it (it contains the tile's barriers).
+template <int W, int DW>
+__device__ WalkResult stage_and_walk(TileSmem<W, DW>& sm, const uint8_t* g, uint32_t L,
+                                     const float* gains) {
+    constexpr uint32_t cap = TileSmem<W, DW>::kStageData;
     const bool fits = L <= cap;
-    uint32_t delta = stage_bytes(sm, g, fits ? L : cap, gains);
-    uint32_t pos = 0, bad_from = kNch;
     if (fits) {
-        // the whole FED is staged; lane k (mod 64) keeps channel k's record position and length.
-        // Branch-free steps: after the first record that does not fit, pos stays put and the
-        // remaining steps only re-read (inside the stage) without effect.
-        constexpr uint32_t omax = TileSmem<D>::kStageBytes - 2;
-        uint32_t vpos0 = 0, vpos1 = 0, vlen0 = 0, vlen1 = 0;
-        auto step = [&](uint32_t k, uint32_t& vpos, uint32_t& vlen) {
-            uint32_t o = pos + delta;
-            o = o < omax ? o : omax;
-            const uint32_t P =
-                uni((uint32_t)sm.u.stage[o] | ((uint32_t)sm.u.stage[o + 1] << 8));
-            const bool ok = bad_from == (uint32_t)kNch && pos + 2 <= L && pos + 2 + P <= L;
-            bad_from = (bad_from == (uint32_t)kNch && !ok) ? k : bad_from;
-            const bool mine = lane() == (k & 63u);
-            vpos = mine ? pos + 2 : vpos;
-            vlen = mine ? P : vlen;
-            pos = ok ? pos + 2 + P : pos;
-        };
+        const uint32_t delta = stage_bytes<kWave * W>(sm, threadIdx.x, g, L, gains);
+        tile_sync();
+        if (wave_index<W>() == 0u) {
+            // lane k (mod 64) keeps channel k's record position and length. Branch-free steps:
+            // after the first record that does not fit the FED, pos stays put and the remaining
+            // steps only re-read (inside the stage) without effect.
+            constexpr uint32_t omax = TileSmem<W, DW>::kStageBytes - 2;
+            uint32_t pos = 0, bad_from = kNch;
+            uint32_t vpos0 = 0, vpos1 = 0, vlen0 = 0, vlen1 = 0;
+            auto step = [&](uint32_t k, uint32_t& vpos, uint32_t& vlen) {
+                uint32_t o = pos + delta;
+                o = o < omax ? o : omax;
+                const uint32_t P =
+                    uni((uint32_t)sm.stage[o] | ((uint32_t)sm.stage[o + 1] << 8));
+                const bool ok = bad_from == (uint32_t)kNch && pos + 2 <= L && pos + 2 + P <= L;
+                bad_from = (bad_from == (uint32_t)kNch && !ok) ? k : bad_from;
+                const bool mine = lane() == (k & 63u);
+                vpos = mine ? pos + 2 : vpos;
+                vlen = mine ? P : vlen;
+                pos = ok ? pos + 2 + P : pos;
+            };
 #pragma unroll 8
-        for (uint32_t k = 0; k < 64u; ++k) step(k, vpos0, vlen0);
+            for (uint32_t k = 0; k < 64u; ++k) step(k, vpos0, vlen0);
 #pragma unroll 8
-        for (uint32_t k = 64; k < (uint32_t)kNch; ++k) step(k, vpos1, vlen1);
-        sm.ch_pos[lane()] = vpos0;
-        sm.ch_len[lane()] = (uint16_t)vlen0;
-        sm.ch_pos[64 + lane()] = vpos1;   // entries 96..127 are never read
-        sm.ch_len[64 + lane()] = (uint16_t)vlen1;
+            for (uint32_t k = 64; k < (uint32_t)kNch; ++k) step(k, vpos1, vlen1);
+            sm.ch_pos[lane()] = vpos0;
+            sm.ch_len[lane()] = (uint16_t)vlen0;
+            sm.ch_pos[64 + lane()] = vpos1;   // entries 96..127 are never read
+            sm.ch_len[64 + lane()] = (uint16_t)vlen1;
+            sm.walk[0] = bad_from;
+            sm.walk[1] = (bad_from == (uint32_t)kNch && pos < L) ? 1u : 0u;
+            sm.walk[2] = delta;
+        }
     } else {
-        // larger than the stage: windows of the FED are staged in turn
-        uint32_t win = 0, win_n = cap;
-        for (uint32_t k = 0; k < (uint32_t)kNch; ++k) {
-            if (pos + 2 > L) { bad_from = k; break; }
-            if (pos + 2 > win + win_n) {
-                tile_sync();
-                win = pos;
-                win_n = (L - win) < cap ? (L - win) : cap;
-                delta = stage_bytes(sm, g + win, win_n, nullptr);
+        // larger than the stage: wave 0 stages windows of the FED in turn and walks them; the
+        // records are then read from global memory
+        if (gains) {
+            if (wave_index<W>() == 0u) store_gain_vec(sm, load_gain_vec(gains));
+        }
+        if (wave_index<W>() == 0u) {
+            uint32_t pos = 0, bad_from = kNch, win = 0, win_n = 0, delta = 0;
+            for (uint32_t k = 0; k < (uint32_t)kNch; ++k) {
+                if (pos + 2 > L) { bad_from = k; break; }
+                if (pos + 2 > win + win_n) {
+                    wave_sync();
+                    win = pos;
+                    win_n = (L - win) < cap ? (L - win) : cap;
+                    delta = stage_bytes<kWave>(sm, lane(), g + win, win_n, nullptr);
+                    wave_sync();
+                }
+                const uint32_t o = pos - win + delta;
+                const uint32_t P =
+                    uni((uint32_t)sm.stage[o] | ((uint32_t)sm.stage[o + 1] << 8));
+                if (pos + 2 + P > L) { bad_from = k; break; }
+                sm.ch_pos[k] = pos + 2;   // the same values from every lane
+                sm.ch_len[k] = (uint16_t)P;
+                pos += 2 + P;
             }
-            const uint32_t o = pos - win + delta;
-            const uint32_t P =
-                uni((uint32_t)sm.u.stage[o] | ((uint32_t)sm.u.stage[o + 1] << 8));
-            if (pos + 2 + P > L) { bad_from = k; break; }
-            sm.ch_pos[k] = pos + 2;   // the same values from every lane
-            sm.ch_len[k] = (uint16_t)P;
-            pos += 2 + P;
+            sm.walk[0] = bad_from;
+            sm.walk[1] = (bad_from == (uint32_t)kNch && pos < L) ? 1u : 0u;
+            sm.walk[2] = 0u;
         }
     }
     tile_sync();
     WalkResult w;
-    w.bad_from = bad_from;
-    w.trailing = (bad_from == (uint32_t)kNch && pos < L) ? 1u : 0u;
+    w.bad_from = uni(sm.walk[0]);
+    w.trailing = uni(sm.walk[1]);
+    w.delta = uni(sm.walk[2]);
     w.fits = fits ? 1u : 0u;
-    w.delta = delta;
     return w;
 }
 
 // ---- record validation, one lane per channel ----------------------------------------------
 // Returns the channel's digi count (0 if malformed) and writes its status into ch_st.
-template <class P, int D>
-__device__ __forceinline__ uint32_t check_channel(TileSmem<D>& sm, P src, uint32_t ch,
+template <class P, int W, int DW>
+__device__ __forceinline__ uint32_t check_channel(TileSmem<W, DW>& sm, P src, uint32_t ch,
                                                   const WalkResult& w) {
     uint32_t st = w.trailing ? (uint32_t)SC_CH_FED_TRAILING : 0u;
     uint32_t nd = 0;
@@ -292,52 +320,56 @@ __device__ __forceinline__ uint32_t check_channel(TileSmem<D>& sm, P src, uint32
     return nd;
 }
 
-// Channel digi counts -> prefix (ch_base) and chunk split; returns the number of chunks.
-template <int D, class CountFn>
-__device__ uint32_t plan_chunks(TileSmem<D>& sm, CountFn count, uint32_t& total) {
+// The channel group [c_lo, c_hi) of wave w: digi counts -> offsets in the group (ch_base) and
+// its split into chunks of at most DW digis; returns the number of chunks. Wave-local.
+template <int W, int DW, class CountFn>
+__device__ uint32_t plan_chunks(TileSmem<W, DW>& sm, uint32_t w, uint32_t c_lo, uint32_t c_hi,
+                                CountFn count, uint32_t& total) {
     uint32_t carry = 0;
-    for (uint32_t base = 0; base < (uint32_t)kNch; base += kWave) {
+    for (uint32_t base = c_lo; base < c_hi; base += kWave) {
         const uint32_t ch = base + lane();
-        const uint32_t nd = ch < (uint32_t)kNch ? count(ch) : 0u;
+        const uint32_t nd = ch < c_hi ? count(ch) : 0u;
         uint32_t tot;
         const uint32_t ex = wave_excl_scan(nd, tot);
-        if (ch < (uint32_t)kNch) sm.ch_base[ch] = carry + ex;
+        if (ch < c_hi) sm.ch_base[ch + w] = carry + ex;
         carry += tot;
     }
     total = carry;
-    sm.ch_base[kNch] = carry;   // uniform stores from every lane
+    sm.ch_base[c_hi + w] = carry;   // uniform stores from every lane
+    uint8_t* cf = sm.chunk_first[w];
     uint32_t n_chunks = 1;
-    if (total <= (uint32_t)D) {
-        sm.chunk_first[0] = 0;
-        sm.chunk_first[1] = kNch;
+    wave_sync();
+    if (total <= (uint32_t)DW) {
+        cf[0] = (uint8_t)c_lo;
+        cf[1] = (uint8_t)c_hi;
     } else {
         // every lane walks the same greedy split (uniform values, same stores)
-        tile_sync();
-        uint32_t c = 0, n = 0;
-        sm.chunk_first[0] = 0;
-        while (c < (uint32_t)kNch) {
-            const uint32_t start = uni(sm.ch_base[c]);
-            uint32_t c1 = c + 1;   // one channel holds <= 256 <= D digis
-            while (c1 < (uint32_t)kNch && uni(sm.ch_base[c1 + 1]) - start <= (uint32_t)D) ++c1;
-            sm.chunk_first[++n] = (uint8_t)c1;
+        uint32_t c = c_lo, n = 0;
+        cf[0] = (uint8_t)c_lo;
+        while (c < c_hi) {
+            const uint32_t start = uni(sm.ch_base[c + w]);
+            uint32_t c1 = c + 1;   // one channel holds <= 256 <= DW digis
+            while (c1 < c_hi && uni(sm.ch_base[c1 + 1 + w]) - start <= (uint32_t)DW) ++c1;
+            cf[++n] = (uint8_t)c1;
             c = c1;
         }
         n_chunks = n;
     }
-    tile_sync();
+    wave_sync();
     return n_chunks;
 }
 
-// Expand the records of channels [c0, c1) into the digi list (one lane per channel); the ADC
+// Expand the records of channels [c0, c1) into the digi list dl (one lane per channel); the ADC
 // bytes of a run are read four at a time.
-template <class P, int D>
-__device__ __forceinline__ void build_zs(TileSmem<D>& sm, P src, uint32_t c0, uint32_t c1) {
-    const uint32_t b0 = sm.ch_base[c0];
+template <class P, int W, int DW>
+__device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, uint32_t* dl, P src,
+                                         uint32_t c0, uint32_t c1) {
+    const uint32_t b0 = sm.ch_base[c0 + w];
     for (uint32_t ch = c0 + lane(); ch < c1; ch += kWave) {
         if (sm.ch_st[ch] & SC_CH_MALFORMED) continue;
         const uint32_t p = sm.ch_pos[ch];
         const uint32_t len = sm.ch_len[ch];
-        uint32_t o = sm.ch_base[ch] - b0;
+        uint32_t o = sm.ch_base[ch + w] - b0;
         uint32_t q = 0;
         while (q < len) {
             const uint32_t first = src[p + q], cnt = src[p + q + 1];
@@ -347,24 +379,24 @@ __device__ __forceinline__ void build_zs(TileSmem<D>& sm, P src, uint32_t c0, ui
             for (; i + 4 <= cnt; i += 4) {
                 const uint32_t a0 = src[s + i], a1 = src[s + i + 1], a2 = src[s + i + 2],
                                a3 = src[s + i + 3];
-                sm.digi[o + i] = base + (i << 8) + a0;
-                sm.digi[o + i + 1] = base + ((i + 1) << 8) + a1;
-                sm.digi[o + i + 2] = base + ((i + 2) << 8) + a2;
-                sm.digi[o + i + 3] = base + ((i + 3) << 8) + a3;
+                dl[o + i] = base + (i << 8) + a0;
+                dl[o + i + 1] = base + ((i + 1) << 8) + a1;
+                dl[o + i + 2] = base + ((i + 2) << 8) + a2;
+                dl[o + i + 3] = base + ((i + 3) << 8) + a3;
             }
-            for (; i < cnt; ++i) sm.digi[o + i] = base + (i << 8) + src[s + i];
+            for (; i < cnt; ++i) dl[o + i] = base + (i << 8) + src[s + i];
             o += cnt;
             q += 2 + cnt;
         }
     }
-    tile_sync();
+    wave_sync();
 }
 
 // Dense rows of channels [c0, c1) -> digi list; 4 channels per wave step, 16 lanes x 16 strips.
-template <int D>
-__device__ __forceinline__ void build_dense(TileSmem<D>& sm, const uint8_t* rows, uint32_t c0,
-                                            uint32_t c1) {
-    const uint32_t b0 = sm.ch_base[c0];
+template <int W, int DW>
+__device__ __forceinline__ void build_dense(TileSmem<W, DW>& sm, uint32_t w, uint32_t* dl,
+                                            const uint8_t* rows, uint32_t c0, uint32_t c1) {
+    const uint32_t b0 = sm.ch_base[c0 + w];
     for (uint32_t cb = c0; cb < c1; cb += 4) {
         const uint32_t ch = cb + (lane() >> 4);
         const uint32_t s0 = (lane() & 15) * 16;
@@ -377,16 +409,16 @@ __device__ __forceinline__ void build_dense(TileSmem<D>& sm, const uint8_t* rows
         uint32_t tot;
         uint32_t o = seg16_excl_scan(cnt, tot);
         if (ch < c1) {
-            o += sm.ch_base[ch] - b0;
+            o += sm.ch_base[ch + w] - b0;
             const uint32_t base = (ch << 16) | (s0 << 8);
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const uint32_t a = (wds[k >> 2] >> ((k & 3) * 8)) & 255u;
-                if (a) sm.digi[o++] = base + ((uint32_t)k << 8) + a;
+                if (a) dl[o++] = base + ((uint32_t)k << 8) + a;
             }
         }
     }
-    tile_sync();
+    wave_sync();
 }
 
 // digi count of one dense channel row (16-byte loads)
@@ -423,24 +455,27 @@ __device__ __forceinline__ bool run_accepted(uint32_t Qs, float S, float t_clust
     return (Qs >> 31) != 0u && (float)(Qs & 0xffffu) >= t_cluster * __builtin_sqrtf(S);
 }
 
-// One step of 64 digis [base, base+64): flags, gain-corrected ADCs, runs, cluster threshold.
-// Every lane takes part (no divergent cross-lane work). Rewrites the digi words (run position,
-// flags), stores c, marks accepted run heads and counts clusters / member ADCs.
-template <int D>
-__device__ __forceinline__ void form_step(TileSmem<D>& sm, uint32_t base, uint32_t nd,
-                                          uint32_t d, float n, const DeviceCalib& cal,
-                                          OpenRun& open, uint32_t& n_cl, uint32_t& my_adc) {
+// Local run position of each lane's digi in a step: distance to the nearest run head at or below
+// (lane 0 heads the part of its run that lies in the step). lhead: that head's lane.
+__device__ __forceinline__ uint32_t local_run_pos(bool act, bool cont, uint32_t& lhead) {
+    const uint64_t lh = __ballot(act && (!cont || lane() == 0u));
+    const uint64_t upto = lh & mask_le();
+    lhead = upto ? 63u - (uint32_t)__clzll((long long)upto) : 0u;
+    return act ? lane() - lhead : 0u;
+}
+
+// One step of 64 digis [base, base+64) of the list dl: flags, runs, cluster threshold. Every
+// lane takes part (no divergent cross-lane work). Adds the flag bits to the digi words, marks
+// accepted run heads and counts clusters / member ADCs.
+__device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t nd, uint32_t d,
+                                          float n, const DeviceCalib& cal, OpenRun& open,
+                                          uint32_t& n_cl, uint32_t& my_adc) {
     const uint32_t j = base + lane();
     const bool valid = j < nd;
-    const uint32_t a = d_low(d), strip = d_strip(d), ch = d_ch(d), pos = d_pos(d);
+    const uint32_t a = d_adc(d), strip = d_strip(d), pos = d_pos(d);
     const float af = (float)a;
     const bool act = valid && af > cal.t_channel * n;
     const bool sd = act && af > cal.t_seed * n;
-    uint32_t c = 0;
-    if (act) {
-        const float q = __builtin_rintf(af / sm.gain[2 * ch + (strip >> 7)]);
-        c = q > 65535.0f ? 65535u : (uint32_t)q;
-    }
     // continues the previous digi: both active, same channel, adjacent strips
     const uint32_t key = act ? pos + 1u : kNoKey;
     uint32_t pk = from_prev_lane(key);
@@ -450,16 +485,13 @@ __device__ __forceinline__ void form_step(TileSmem<D>& sm, uint32_t base, uint32
     // the run open at the end of the previous step ends before this step: decide it now
     if (open.key != kNoKey && !cont0) {
         if (run_accepted(open.Q, open.S, cal.t_cluster)) {
-            sm.digi[open.head] |= kAccBit;   // same word, same value from every lane
+            dl[open.head] |= kAccBit;   // same word, same value from every lane
             n_cl += 1;
             my_adc += lane() == 0u ? open.rp + 1u : 0u;
         }
     }
-    // local run position: distance to the nearest head at or below (lane 0 heads its run here)
-    const uint64_t lh = __ballot(act && (!cont || lane() == 0u));
-    const uint64_t upto = lh & mask_le();
-    const uint32_t lhead = upto ? 63u - (uint32_t)__clzll((long long)upto) : 0u;
-    const uint32_t lrp = act ? lane() - lhead : 0u;
+    uint32_t lhead;
+    const uint32_t lrp = local_run_pos(act, cont, lhead);
     const bool from_open = cont0 && lhead == 0u;   // my run began in an earlier step
     const uint32_t rp = lrp + ((act && from_open) ? open.rp + 1u : 0u);
     // sums along the run: S by sequential fmaf from the left strip, raw charge, seed seen
@@ -477,18 +509,13 @@ __device__ __forceinline__ void form_step(TileSmem<D>& sm, uint32_t base, uint32
         S = upd ? __builtin_fmaf(n, n, Sp) : S;
         Qs = upd ? ((a + (Qp & 0xffffu)) | ((Qp | Qs) & 0x80000000u)) : Qs;
     }
-    // digi words after forming, and the gain-corrected ADCs
-    if (valid) {
-        sm.digi[j] = rp | (d & 0x7fff00u) | (act ? kActBit : 0u) | (sd ? kSeedBit : 0u) |
-                     (cont ? kContBit : 0u);
-        sm.u.c[j] = (uint16_t)c;
-    }
+    if (valid) dl[j] = d | (act ? kActBit : 0u) | (sd ? kSeedBit : 0u) | (cont ? kContBit : 0u);
     // runs that end inside this step (lane 63's run may go on: it stays open)
     const bool next_cont = from_next_lane(cont ? 1u : 0u) != 0u;
     const bool ends = act && !next_cont && lane() != 63u;
     const bool acc = ends && run_accepted(Qs, S, cal.t_cluster);
     if (acc) {
-        sm.digi[j - rp] |= kAccBit;
+        dl[j - rp] |= kAccBit;
         my_adc += rp + 1u;
     }
     n_cl += popc(__ballot(acc));
@@ -499,9 +526,8 @@ __device__ __forceinline__ void form_step(TileSmem<D>& sm, uint32_t base, uint32
     open.Q = last_lane(Qs);
 }
 
-// Forming over the digi list [0, nd): steps of 64 digis, the loads of kBatch steps in flight.
-template <int D>
-__device__ __forceinline__ void form_pass(TileSmem<D>& sm, uint32_t nd, const DeviceCalib& cal,
+// Forming over the digi list dl[0, nd): steps of 64 digis, the loads of kBatch steps in flight.
+__device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const DeviceCalib& cal,
                                           uint32_t fed, uint32_t& n_cl, uint32_t& n_adc) {
     constexpr int kBatch = 4;
     gconst<float>* noise = gc(cal.noise) + fed * kStripsPerFed;
@@ -513,7 +539,7 @@ __device__ __forceinline__ void form_pass(TileSmem<D>& sm, uint32_t nd, const De
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
             const uint32_t j = b + (uint32_t)(k * kWave) + lane();
-            d[k] = j < nd ? sm.digi[j] : 0u;
+            d[k] = j < nd ? dl[j] : 0u;
         }
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
@@ -523,17 +549,17 @@ __device__ __forceinline__ void form_pass(TileSmem<D>& sm, uint32_t nd, const De
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
             const uint32_t base = b + (uint32_t)(k * kWave);
-            if (base < nd) form_step(sm, base, nd, d[k], n[k], cal, open, ncl, my_adc);
+            if (base < nd) form_step(dl, base, nd, d[k], n[k], cal, open, ncl, my_adc);
         }
     }
     if (open.key != kNoKey && run_accepted(open.Q, open.S, cal.t_cluster)) {
-        sm.digi[open.head] |= kAccBit;
+        dl[open.head] |= kAccBit;
         ncl += 1;
         my_adc += lane() == 0u ? open.rp + 1u : 0u;
     }
     n_cl = ncl;
     n_adc = wave_sum(my_adc);
-    tile_sync();
+    wave_sync();
 }
 
 // ---- outputs ------------------------------------------------------------------------------
@@ -541,12 +567,14 @@ __device__ __forceinline__ void form_pass(TileSmem<D>& sm, uint32_t nd, const De
 struct OpenCluster {
     uint32_t open;   // 1: lane 63 of the previous step was a member
     uint32_t acc;    // acceptance of the run at lane 63 (for the continuing lanes)
+    uint32_t rp;     // run position of lane 63's digi
     uint32_t C, M;   // sums of c and strip*c so far
     uint32_t last;   // digi word of its last digi
 };
 
-__device__ __forceinline__ u32x4 make_record(uint32_t fed, uint32_t dw, uint32_t C, uint32_t M) {
-    const uint32_t rp = d_low(dw), strip = d_strip(dw);
+__device__ __forceinline__ u32x4 make_record(uint32_t fed, uint32_t dw, uint32_t rp, uint32_t C,
+                                             uint32_t M) {
+    const uint32_t strip = d_strip(dw);
     const uint32_t first = strip - rp, width = rp + 1u;
     // barycenter: sum (s+1/2) c / sum c = (2M + C) / (2C), numerator and denominator exact
     const float bary = C ? (float)((double)(2ull * M + C) / (2.0 * (double)C))
@@ -554,26 +582,26 @@ __device__ __forceinline__ u32x4 make_record(uint32_t fed, uint32_t dw, uint32_t
     return u32x4{fed * kNch + d_ch(dw), first | (width << 16), C, __float_as_uint(bary)};
 }
 
-// Records and member ADCs of the digi list [0, nd) at their final positions.
-template <int D>
-__device__ __forceinline__ void write_pass(TileSmem<D>& sm, uint32_t nd, uint32_t fed,
-                                           const EventDesc& ev, uint32_t base_cl,
-                                           uint32_t base_adc) {
+// Records and member ADCs of the digi list dl[0, nd) at their final positions. The member ADCs
+// are gain-corrected here: c = min(rint(adc / gain), 65535) with the FP32 quotient.
+template <int W, int DW>
+__device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint32_t* dl,
+                                           uint32_t nd, uint32_t fed, const EventDesc& ev,
+                                           uint32_t base_cl, uint32_t base_adc) {
     gmut<uint16_t>* adc_out = gm(ev.adc);
     gmut<u32x4>* cl_out = gm(reinterpret_cast<u32x4*>(ev.cl));
-    OpenCluster oc{0u, 0u, 0u, 0u, 0u};
+    OpenCluster oc{0u, 0u, 0u, 0u, 0u, 0u};
     uint32_t rc = base_cl, pa = base_adc;
     for (uint32_t base = 0; base < nd; base += kWave) {
         const uint32_t j = base + lane();
         const bool valid = j < nd;
-        const uint32_t d = valid ? sm.digi[j] : 0u;
-        const uint32_t c = valid ? (uint32_t)sm.u.c[j] : 0u;
+        const uint32_t d = valid ? dl[j] : 0u;
         const bool act = (d & kActBit) != 0u;
         const bool cont = (d & kContBit) != 0u;
         const bool cont0 = (__ballot(cont) & 1ull) != 0ull;
         // the cluster open at the end of the previous step is complete unless lane 0 continues it
         if (oc.open && !cont0) {
-            if (rc < ev.cap_cl) cl_out[rc] = make_record(fed, oc.last, oc.C, oc.M);
+            if (rc < ev.cap_cl) cl_out[rc] = make_record(fed, oc.last, oc.rp, oc.C, oc.M);
             rc += 1;
         }
         // members: active digis whose run head is accepted
@@ -584,17 +612,25 @@ __device__ __forceinline__ void write_pass(TileSmem<D>& sm, uint32_t nd, uint32_
         const bool run_acc = hb_le ? ((ab >> (63u - (uint32_t)__clzll((long long)hb_le))) & 1ull)
                                    : (oc.acc != 0u);
         const bool member = act && run_acc;
+        uint32_t c = 0;
+        if (member) {
+            const float q = __builtin_rintf((float)d_adc(d) /
+                                            sm.gain[2 * d_ch(d) + (d_strip(d) >> 7)]);
+            c = q > 65535.0f ? 65535u : (uint32_t)q;
+        }
         const uint64_t mb = __ballot(member);
         if (member) {
             const uint32_t p = pa + popc(mb & mask_lt());
             if (p < ev.cap_adc) adc_out[p] = (uint16_t)c;
         }
         pa += popc(mb);
-        // charge and strip-weighted charge along member runs
-        const uint32_t rp = d_low(d);
-        const uint32_t lrp = member ? (rp < lane() ? rp : lane()) : 0u;
-        uint32_t C = member ? c : 0u;
-        uint32_t M = member ? d_strip(d) * c : 0u;
+        // run positions, charge and strip-weighted charge along member runs
+        uint32_t lhead;
+        const uint32_t lrp0 = local_run_pos(act, cont, lhead);
+        const uint32_t rp = lrp0 + ((act && cont0 && lhead == 0u) ? oc.rp + 1u : 0u);
+        const uint32_t lrp = member ? lrp0 : 0u;
+        uint32_t C = c;
+        uint32_t M = d_strip(d) * c;
         if (cont0 && oc.open) {
             const bool l0 = lane() == 0u;
             C = l0 ? C + oc.C : C;
@@ -611,24 +647,25 @@ __device__ __forceinline__ void write_pass(TileSmem<D>& sm, uint32_t nd, uint32_
         const uint64_t eb = __ballot(ends);
         if (ends) {
             const uint32_t p = rc + popc(eb & mask_lt());
-            if (p < ev.cap_cl) cl_out[p] = make_record(fed, d, C, M);
+            if (p < ev.cap_cl) cl_out[p] = make_record(fed, d, rp, C, M);
         }
         rc += popc(eb);
         oc.open = (uint32_t)(mb >> 63);
         oc.acc = (uint32_t)((__ballot(run_acc) >> 63) & 1ull);
+        oc.rp = last_lane(rp);
         oc.C = last_lane(C);
         oc.M = last_lane(M);
         oc.last = last_lane(d);
     }
-    if (oc.open && rc < ev.cap_cl) cl_out[rc] = make_record(fed, oc.last, oc.C, oc.M);
-    tile_sync();
+    if (oc.open && rc < ev.cap_cl) cl_out[rc] = make_record(fed, oc.last, oc.rp, oc.C, oc.M);
+    wave_sync();
 }
 
-// ---- decoupled look-back over the FEDs of one event ---------------------------------------
-// Publishes this FED's counts and sums those of the FEDs before it: lane i reads the word of FED
-// top-i, so 64 predecessors are inspected per load; only words not yet published are waited
-// for. Only the counts travel through these words, so relaxed atomics suffice. All values
-// steering the loop are uniform.
+// ---- decoupled look-back over the channel groups of one event -----------------------------
+// Publishes this group's counts and sums those of the groups before it: lane i reads the word
+// of group top-i, so 64 predecessors are inspected per load; only words not yet published are
+// waited for. Only the counts travel through these words, so relaxed atomics suffice. All
+// values steering the loop are uniform.
 __device__ __forceinline__ void publish_and_lookback(unsigned long long* row, uint32_t f,
                                                      uint32_t n_cl, uint32_t n_adc,
                                                      uint32_t& ex_cl, uint32_t& ex_adc,
@@ -640,11 +677,11 @@ __device__ __forceinline__ void publish_and_lookback(unsigned long long* row, ui
     } else {
         __hip_atomic_store(&row[f], pack_state(kFlagAgg, n_cl, n_adc), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        int top = (int)f - 1;   // highest FED not yet summed
+        int top = (int)f - 1;   // highest group not yet summed
         uint32_t spins = 0;
         for (;;) {
             const int k = top - (int)lane();
-            unsigned long long v = pack_state(kFlagIncl, 0u, 0u);   // before FED 0: nothing
+            unsigned long long v = pack_state(kFlagIncl, 0u, 0u);   // before group 0: nothing
             if (k >= 0) v = __hip_atomic_load(&row[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t flag = (uint32_t)(v >> 62);
             const uint64_t incl = __ballot(flag == kFlagIncl);
@@ -658,7 +695,7 @@ __device__ __forceinline__ void publish_and_lookback(unsigned long long* row, ui
             aadc += wave_sum(take ? (uint32_t)(v & 0x7fffffffu) : 0u);
             if (first_incl < first_none) break;      // reached an inclusive word
             top -= (int)n_take;
-            if (first_none < 64u) {                  // FED `top` has not published yet
+            if (first_none < 64u) {                  // group `top` has not published yet
                 if (++spins > kSpinLimit) { e = 1; break; }
                 __builtin_amdgcn_s_sleep(2);
             }
@@ -671,12 +708,13 @@ __device__ __forceinline__ void publish_and_lookback(unsigned long long* row, ui
     err = e;
 }
 
-// Status bits of the FED's channels -> optional per-channel output and the event's flags.
-template <int D>
-__device__ __forceinline__ void emit_status(TileSmem<D>& sm, uint8_t* chan_status, uint32_t f,
+// Status bits of channels [c_lo, c_hi) -> optional per-channel output and the event's flags.
+template <int W, int DW>
+__device__ __forceinline__ void emit_status(TileSmem<W, DW>& sm, uint32_t c_lo, uint32_t c_hi,
+                                            uint8_t* chan_status, uint32_t f,
                                             uint32_t* flags_out) {
     uint32_t any = 0;
-    for (uint32_t ch = lane(); ch < (uint32_t)kNch; ch += kWave) {
+    for (uint32_t ch = c_lo + lane(); ch < c_hi; ch += kWave) {
         const uint32_t st = sm.ch_st[ch];
         if (chan_status) gm(chan_status)[f * kNch + ch] = (uint8_t)st;
         any |= st;
@@ -687,58 +725,67 @@ __device__ __forceinline__ void emit_status(TileSmem<D>& sm, uint8_t* chan_statu
     if (bits) atomicOr(flags_out, bits);   // uniform branch; every lane ORs the same bits
 }
 
-// The cluster stages of one tile over its chunks (shared by the ZS and the dense front ends).
-// build(c0, c1, stage_valid) fills the digi list of channels [c0, c1).
-template <int D, class BuildFn>
-__device__ void cluster_chunks(const FusedArgs& A, TileSmem<D>& sm, const EventDesc& ev,
-                               uint32_t e, uint32_t f, uint32_t n_chunks, uint32_t total,
-                               BuildFn build) {
+// The cluster stages of one channel group over its chunks (wave-local; shared by the ZS and the
+// dense front ends). build(c0, c1) fills the group's digi list with channels [c0, c1).
+template <int W, int DW, class BuildFn>
+__device__ void cluster_group(const FusedArgs& A, TileSmem<W, DW>& sm, const EventDesc& ev,
+                              uint32_t e, uint32_t f, uint32_t w, uint32_t n_chunks,
+                              uint32_t total, BuildFn build) {
     const uint32_t n_fed = A.cal.n_fed;
-    unsigned long long* row = A.tile_state + (size_t)e * n_fed;
+    unsigned long long* row = A.tile_state + (size_t)e * n_fed * W;
+    const uint32_t grp = f * W + w;   // look-back index of this channel group
+    uint32_t* dl = sm.digi + w * DW;
+    const uint8_t* cf = sm.chunk_first[w];
     uint32_t n_cl = 0, n_adc = 0, ex_cl = 0, ex_adc = 0, err = 0;
     if (n_chunks == 1) {
-        build(0u, (uint32_t)kNch, true);
-        form_pass(sm, total, A.cal, f, n_cl, n_adc);
-        publish_and_lookback(row, f, n_cl, n_adc, ex_cl, ex_adc, err);
-        write_pass(sm, total, f, ev, ex_cl, ex_adc);
+        build(uni(cf[0]), uni(cf[1]));
+        form_pass(dl, total, A.cal, f, n_cl, n_adc);
+        publish_and_lookback(row, grp, n_cl, n_adc, ex_cl, ex_adc, err);
+        write_pass(sm, dl, total, f, ev, ex_cl, ex_adc);
     } else {
         // counts of every chunk first, then the look-back, then the chunks again with writes
         for (int pass = 0; pass < 2; ++pass) {
             uint32_t bc = 0, ba = 0;
             if (pass == 1) {
-                publish_and_lookback(row, f, n_cl, n_adc, ex_cl, ex_adc, err);
+                publish_and_lookback(row, grp, n_cl, n_adc, ex_cl, ex_adc, err);
                 bc = ex_cl;
                 ba = ex_adc;
             }
             for (uint32_t ci = 0; ci < n_chunks; ++ci) {
-                const uint32_t c0 = uni(sm.chunk_first[ci]), c1 = uni(sm.chunk_first[ci + 1]);
-                build(c0, c1, pass == 0 && ci == 0);
-                const uint32_t nd = uni(sm.ch_base[c1] - sm.ch_base[c0]);
+                const uint32_t c0 = uni(cf[ci]), c1 = uni(cf[ci + 1]);
+                build(c0, c1);
+                const uint32_t nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
                 uint32_t ccl, cadc;
-                form_pass(sm, nd, A.cal, f, ccl, cadc);
+                form_pass(dl, nd, A.cal, f, ccl, cadc);
                 if (pass == 0) {
                     n_cl += ccl;
                     n_adc += cadc;
                 } else {
-                    write_pass(sm, nd, f, ev, bc, ba);
+                    write_pass(sm, dl, nd, f, ev, bc, ba);
                     bc += ccl;
                     ba += cadc;
                 }
-                tile_sync();
             }
         }
     }
     // uniform branches; every lane stores the same values
     if (err) atomicOr(&A.res[e].flags, kResSpinTimeout);
-    if (f == n_fed - 1) {
+    if (f == n_fed - 1 && w == W - 1) {
         A.res[e].n_cl = ex_cl + n_cl;
         A.res[e].n_adc = ex_adc + n_adc;
     }
 }
 
+// Channel group of wave w: [c_lo, c_hi).
+template <int W>
+__device__ __forceinline__ void group_range(uint32_t w, uint32_t& c_lo, uint32_t& c_hi) {
+    c_lo = w * (uint32_t)(kNch / W);
+    c_hi = c_lo + (uint32_t)(kNch / W);
+}
+
 // ---- one (event, FED) tile from ZS bytes --------------------------------------------------
-template <int D>
-__device__ void zs_tile(const FusedArgs& A, TileSmem<D>& sm, uint32_t e, uint32_t f) {
+template <int W, int DW>
+__device__ void zs_tile(const FusedArgs& A, TileSmem<W, DW>& sm, uint32_t e, uint32_t f) {
     const EventDesc* evp = A.ev + e;
     EventDesc ev;
     ev.zs = uniptr(evp->zs);
@@ -752,34 +799,36 @@ __device__ void zs_tile(const FusedArgs& A, TileSmem<D>& sm, uint32_t e, uint32_
     const uint32_t L = hi > lo ? (uint32_t)(hi - lo) : 0u;
     const uint8_t* g = ev.zs + lo;
 
-    const WalkResult w = walk_fed(sm, g, L, A.cal.gain + (size_t)f * 2 * kNch);
+    const WalkResult wk = stage_and_walk(sm, g, L, A.cal.gain + (size_t)f * 2 * kNch);
+    const uint32_t w = wave_index<W>();
+    uint32_t c_lo, c_hi;
+    group_range<W>(w, c_lo, c_hi);
     uint32_t total;
     uint32_t n_chunks;
-    if (w.fits) {
-        const uint8_t* st = sm.u.stage + w.delta;
-        n_chunks = plan_chunks(sm, [&](uint32_t ch) { return check_channel(sm, st, ch, w); }, total);
+    if (wk.fits) {
+        const uint8_t* st = sm.stage + wk.delta;
+        n_chunks = plan_chunks(sm, w, c_lo, c_hi,
+                               [&](uint32_t ch) { return check_channel(sm, st, ch, wk); }, total);
     } else {
         gconst<uint8_t>* gg = gc(g);
-        n_chunks = plan_chunks(sm, [&](uint32_t ch) { return check_channel(sm, gg, ch, w); }, total);
+        n_chunks = plan_chunks(sm, w, c_lo, c_hi,
+                               [&](uint32_t ch) { return check_channel(sm, gg, ch, wk); }, total);
     }
-    emit_status(sm, ev.chan_status, f, &A.res[e].flags);
-    const bool fits = w.fits != 0;
-    const uint32_t delta = w.delta;
-    auto build = [&](uint32_t c0, uint32_t c1, bool stage_valid) {
-        if (fits) {
-            // the ADCs of an earlier chunk overwrote the stage
-            if (!stage_valid) stage_bytes(sm, g, L, nullptr);
-            build_zs(sm, (const uint8_t*)(sm.u.stage + delta), c0, c1);
-        } else {
-            build_zs(sm, gc(g), c0, c1);
-        }
+    emit_status(sm, c_lo, c_hi, ev.chan_status, f, &A.res[e].flags);
+    uint32_t* dl = sm.digi + w * DW;
+    const bool fits = wk.fits != 0;
+    const uint32_t delta = wk.delta;
+    auto build = [&](uint32_t c0, uint32_t c1) {
+        if (fits) build_zs(sm, w, dl, (const uint8_t*)(sm.stage + delta), c0, c1);
+        else      build_zs(sm, w, dl, gc(g), c0, c1);
     };
-    cluster_chunks(A, sm, ev, e, f, n_chunks, total, build);
+    cluster_group(A, sm, ev, e, f, w, n_chunks, total, build);
 }
 
 // ---- one FED tile from dense ADC rows (single event) --------------------------------------
-template <int D>
-__device__ void dense_tile(const FusedArgs& A, TileSmem<D>& sm, const uint8_t* dense, uint32_t f) {
+template <int W, int DW>
+__device__ void dense_tile(const FusedArgs& A, TileSmem<W, DW>& sm, const uint8_t* dense,
+                           uint32_t f) {
     const EventDesc* evp = A.ev;
     EventDesc ev;
     ev.zs = nullptr;
@@ -790,13 +839,19 @@ __device__ void dense_tile(const FusedArgs& A, TileSmem<D>& sm, const uint8_t* d
     ev.cap_cl = uni(evp->cap_cl);
     ev.cap_adc = uni(evp->cap_adc);
     const uint8_t* rows = dense + (size_t)f * kStripsPerFed;
-    store_gain_vec(sm, load_gain_vec<D>(A.cal.gain + (size_t)f * 2 * kNch));
-    for (uint32_t ch = lane(); ch < (uint32_t)kNch; ch += kWave) sm.ch_st[ch] = 0;
+    const uint32_t w = wave_index<W>();
+    if (w == 0u) store_gain_vec(sm, load_gain_vec(A.cal.gain + (size_t)f * 2 * kNch));
+    tile_sync();
+    uint32_t c_lo, c_hi;
+    group_range<W>(w, c_lo, c_hi);
+    for (uint32_t ch = c_lo + lane(); ch < c_hi; ch += kWave) sm.ch_st[ch] = 0;
     uint32_t total;
     const uint32_t n_chunks = plan_chunks(
-        sm, [&](uint32_t ch) { return count_dense_row(rows + ch * kStripsPerChannel); }, total);
-    auto build = [&](uint32_t c0, uint32_t c1, bool) { build_dense(sm, rows, c0, c1); };
-    cluster_chunks(A, sm, ev, 0, f, n_chunks, total, build);
+        sm, w, c_lo, c_hi,
+        [&](uint32_t ch) { return count_dense_row(rows + ch * kStripsPerChannel); }, total);
+    uint32_t* dl = sm.digi + w * DW;
+    auto build = [&](uint32_t c0, uint32_t c1) { build_dense(sm, w, dl, rows, c0, c1); };
+    cluster_group(A, sm, ev, 0, f, w, n_chunks, total, build);
 }
 
 // ---- kernels --------------------------------------------------------------------------------
@@ -804,61 +859,72 @@ __device__ void dense_tile(const FusedArgs& A, TileSmem<D>& sm, const uint8_t* d
 // the others (no lane test); lane 0's old value is the tile. Tiles are taken in a global order
 // (FED-major or event-major) in which a tile's look-back predecessors come before it, so the
 // lowest unfinished tile of an event has always been taken and every look-back ends, whatever
-// part of the grid is resident.
-__device__ __forceinline__ uint32_t next_tile(uint32_t* queue) {
-    return uni(atomicAdd(queue, lane() == 0u ? 1u : 0u));
+// part of the grid is resident. With several waves per tile, wave 0 takes the ticket and the
+// others read it after a barrier.
+template <int W, int DW>
+__device__ __forceinline__ uint32_t next_tile(TileSmem<W, DW>& sm, uint32_t* queue) {
+    if constexpr (W == 1) {
+        return uni(atomicAdd(queue, lane() == 0u ? 1u : 0u));
+    } else {
+        if (wave_index<W>() == 0u) sm.walk[3] = uni(atomicAdd(queue, lane() == 0u ? 1u : 0u));
+        tile_sync();
+        const uint32_t t = uni(sm.walk[3]);
+        tile_sync();
+        return t;
+    }
 }
 
 // Runs tile(e, f) for every tile of an n_ev x n_fed launch.
-template <class TileFn>
-__device__ __forceinline__ void run_tiles(uint32_t* queue, uint32_t n_ev, uint32_t n_fed,
-                                          uint32_t fed_major, TileFn tile) {
+template <int W, int DW, class TileFn>
+__device__ __forceinline__ void run_tiles(TileSmem<W, DW>& sm, uint32_t* queue, uint32_t n_ev,
+                                          uint32_t n_fed, uint32_t fed_major, TileFn tile) {
     const uint32_t n_tiles = n_ev * n_fed;
     for (;;) {
-        const uint32_t t = next_tile(queue);
+        const uint32_t t = next_tile(sm, queue);
         if (t >= n_tiles) break;
         uint32_t e, f;
         if (fed_major) { f = t / n_ev; e = t - f * n_ev; }
         else           { e = t / n_fed; f = t - e * n_fed; }
         tile(e, f);
-        tile_sync();   // the tile ends here for every lane (a convergent point)
+        tile_sync();   // the tile ends here for every lane of every wave (a convergent point)
     }
 }
 
-template <int D>
-__global__ __launch_bounds__(kWave) void fused_kernel(FusedArgs A) {
-    __shared__ TileSmem<D> sm;
-    run_tiles(A.queue, A.n_ev, A.cal.n_fed, A.fed_major,
-              [&](uint32_t e, uint32_t f) { zs_tile<D>(A, sm, e, f); });
+template <int W, int DW>
+__global__ __launch_bounds__(kWave * W) void fused_kernel(FusedArgs A) {
+    __shared__ TileSmem<W, DW> sm;
+    run_tiles(sm, A.queue, A.n_ev, A.cal.n_fed, A.fed_major,
+              [&](uint32_t e, uint32_t f) { zs_tile<W, DW>(A, sm, e, f); });
 }
 
-template <int D>
-__global__ __launch_bounds__(kWave) void cluster_dense_kernel(const uint8_t* dense, FusedArgs A) {
-    __shared__ TileSmem<D> sm;
-    run_tiles(A.queue, 1u, A.cal.n_fed, 1u,
-              [&](uint32_t, uint32_t f) { dense_tile<D>(A, sm, dense, f); });
+template <int W, int DW>
+__global__ __launch_bounds__(kWave * W) void cluster_dense_kernel(const uint8_t* dense, FusedArgs A) {
+    __shared__ TileSmem<W, DW> sm;
+    run_tiles(sm, A.queue, 1u, A.cal.n_fed, 1u,
+              [&](uint32_t, uint32_t f) { dense_tile<W, DW>(A, sm, dense, f); });
 }
 
 // ZS -> dense rows, one FED per single-wave workgroup.
 __global__ __launch_bounds__(kWave) void unpack_kernel(const uint8_t* zs, const uint64_t* fed_off,
                                                        uint8_t* dense, uint8_t* chan_status,
                                                        EventResult* res) {
-    constexpr int D = 1024;
-    __shared__ TileSmem<D> sm;
+    __shared__ TileSmem<1, 1024> sm;
     const uint32_t f = blockIdx.x;
     const uint64_t lo = uni64(gc(fed_off)[f]), hi = uni64(gc(fed_off)[f + 1]);
     const uint32_t L = hi > lo ? (uint32_t)(hi - lo) : 0u;
     const uint8_t* g = zs + lo;
-    const WalkResult w = walk_fed(sm, g, L, nullptr);
+    const WalkResult w = stage_and_walk(sm, g, L, nullptr);
     uint32_t total;
     if (w.fits) {
-        const uint8_t* st = sm.u.stage + w.delta;
-        plan_chunks(sm, [&](uint32_t ch) { return check_channel(sm, st, ch, w); }, total);
+        const uint8_t* st = sm.stage + w.delta;
+        plan_chunks(sm, 0u, 0u, (uint32_t)kNch,
+                    [&](uint32_t ch) { return check_channel(sm, st, ch, w); }, total);
     } else {
         gconst<uint8_t>* gg = gc(g);
-        plan_chunks(sm, [&](uint32_t ch) { return check_channel(sm, gg, ch, w); }, total);
+        plan_chunks(sm, 0u, 0u, (uint32_t)kNch,
+                    [&](uint32_t ch) { return check_channel(sm, gg, ch, w); }, total);
     }
-    emit_status(sm, chan_status, f, &res->flags);
+    emit_status(sm, 0u, (uint32_t)kNch, chan_status, f, &res->flags);
     // 16 channels at a time: zero rows in LDS, expand records, copy out with 16-byte stores
     uint8_t* rowbuf = reinterpret_cast<uint8_t*>(sm.digi);   // 4 KiB
     gmut<u32x4>* out = gm(reinterpret_cast<u32x4*>(dense + (size_t)f * kStripsPerFed));
@@ -874,7 +940,7 @@ __global__ __launch_bounds__(kWave) void unpack_kernel(const uint8_t* zs, const 
                 uint8_t* row = rowbuf + lane() * kStripsPerChannel;
                 uint32_t q = 0;
                 if (w.fits) {
-                    const uint8_t* s = sm.u.stage + w.delta;
+                    const uint8_t* s = sm.stage + w.delta;
                     while (q < len) {
                         const uint32_t first = s[p + q], cnt = s[p + q + 1];
                         for (uint32_t i = 0; i < cnt; ++i) row[first + i] = s[p + q + 2 + i];
@@ -921,34 +987,37 @@ __global__ void derive_calib_kernel(const float* noise, const float* gain, const
     out[i] = usable ? n : __builtin_inff();
 }
 
-template <int D>
+template <int W, int DW>
 int blocks_per_cu_for(bool dense) {
     int nb = 0;
-    hipError_t e = dense ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cluster_dense_kernel<D>, kWave, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_kernel<D>, kWave, 0);
+    hipError_t e = dense ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cluster_dense_kernel<W, DW>, kWave * W, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_kernel<W, DW>, kWave * W, 0);
     return e == hipSuccess ? nb : 1;
 }
 
+// Tile shapes: W waves per tile and chunk_digis digis per tile (chunk_digis / W per wave).
 template <class F>
 bool dispatch(uint32_t w, uint32_t d, F&& f) {
-    if (w != 1) return false;
-#define SC_CASE(DD) \
-    if (d == DD) { f(std::integral_constant<int, DD>{}); return true; }
-    SC_CASE(1024) SC_CASE(2048) SC_CASE(3072) SC_CASE(4096)
+#define SC_CASE(WW, DD) \
+    if (w == WW && d == DD) { f(std::integral_constant<int, WW>{}, std::integral_constant<int, DD / WW>{}); return true; }
+    SC_CASE(1, 1024) SC_CASE(1, 2048) SC_CASE(1, 3072) SC_CASE(1, 4096)
+    SC_CASE(2, 2048) SC_CASE(2, 3072) SC_CASE(2, 4096)
+    SC_CASE(4, 2048) SC_CASE(4, 3072) SC_CASE(4, 4096)
 #undef SC_CASE
     return false;
 }
 
 }  // namespace
 
-// A tile is one wavefront; `waves` other than 1 is not offered.
 bool tile_shape_supported(uint32_t waves, uint32_t d) {
-    return dispatch(waves, d, [](auto) {});
+    return dispatch(waves, d, [](auto, auto) {});
 }
 
 int fused_blocks_per_cu(uint32_t waves, uint32_t d, bool dense) {
     int nb = 1;
-    dispatch(waves, d, [&](auto D) { nb = blocks_per_cu_for<decltype(D)::value>(dense); });
+    dispatch(waves, d, [&](auto W, auto DW) {
+        nb = blocks_per_cu_for<decltype(W)::value, decltype(DW)::value>(dense);
+    });
     return nb;
 }
 
@@ -961,8 +1030,7 @@ hipError_t launch_derive_calib(const float* noise, const float* gain, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_reset(const FusedArgs& a, uint32_t n_fed, hipStream_t stream) {
-    const uint32_t n_state = a.n_ev * n_fed;
+hipError_t launch_reset(const FusedArgs& a, uint32_t n_state, hipStream_t stream) {
     const uint32_t work = n_state > a.n_ev ? n_state : a.n_ev;
     uint32_t blocks = (work + 255) / 256;
     if (blocks < 1) blocks = 1;
@@ -976,9 +1044,9 @@ hipError_t launch_reset(const FusedArgs& a, uint32_t n_fed, hipStream_t stream) 
 hipError_t launch_fused(const FusedArgs& a, uint32_t waves, uint32_t d, uint32_t grid,
                         hipStream_t stream) {
     (void)hipGetLastError();
-    const bool ok = dispatch(waves, d, [&](auto D) {
-        constexpr int dd = decltype(D)::value;
-        hipLaunchKernelGGL((fused_kernel<dd>), dim3(grid), dim3(kWave), 0, stream, a);
+    const bool ok = dispatch(waves, d, [&](auto W, auto DW) {
+        constexpr int w = decltype(W)::value, dw = decltype(DW)::value;
+        hipLaunchKernelGGL((fused_kernel<w, dw>), dim3(grid), dim3(kWave * w), 0, stream, a);
     });
     return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
@@ -986,9 +1054,10 @@ hipError_t launch_fused(const FusedArgs& a, uint32_t waves, uint32_t d, uint32_t
 hipError_t launch_cluster_dense(const uint8_t* dense, const FusedArgs& a, uint32_t waves,
                                 uint32_t d, uint32_t grid, hipStream_t stream) {
     (void)hipGetLastError();
-    const bool ok = dispatch(waves, d, [&](auto D) {
-        constexpr int dd = decltype(D)::value;
-        hipLaunchKernelGGL((cluster_dense_kernel<dd>), dim3(grid), dim3(kWave), 0, stream, dense, a);
+    const bool ok = dispatch(waves, d, [&](auto W, auto DW) {
+        constexpr int w = decltype(W)::value, dw = decltype(DW)::value;
+        hipLaunchKernelGGL((cluster_dense_kernel<w, dw>), dim3(grid), dim3(kWave * w), 0, stream,
+                           dense, a);
     });
     return ok ? hipGetLastError() : hipErrorInvalidValue;
 }

@@ -87,7 +87,8 @@ struct Workspace {
         hipError_t e;
         if ((e = desc.ensure(sizeof(EventDesc) * n_ev)) != hipSuccess) return e;
         if ((e = res.ensure(sizeof(EventResult) * n_ev)) != hipSuccess) return e;
-        if ((e = state.ensure(sizeof(unsigned long long) * (size_t)n_ev * n_fed)) != hipSuccess) return e;
+        // one look-back word per channel group: up to 4 groups per FED
+        if ((e = state.ensure(sizeof(unsigned long long) * (size_t)n_ev * n_fed * 4)) != hipSuccess) return e;
         if ((e = queue.ensure(64)) != hipSuccess) return e;
         if ((e = h_desc.ensure(sizeof(EventDesc) * n_ev)) != hipSuccess) return e;
         if ((e = h_res.ensure(sizeof(EventResult) * n_ev)) != hipSuccess) return e;
@@ -336,7 +337,7 @@ hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bo
     if ((e = hipMemcpyAsync(ws.desc.p, ws.h_desc.p, sizeof(EventDesc) * n, hipMemcpyHostToDevice, s)))
         return e;
     const FusedArgs a = fused_args(c, ws, n);
-    if ((e = launch_reset(a, c->n_fed, s))) return e;
+    if ((e = launch_reset(a, n * c->n_fed * c->tuning.tile_waves, s))) return e;
     if (timed && (e = hipEventRecord(c->ev0, s))) return e;
     const uint32_t grid = grid_for(c, n * c->n_fed, false);
     if ((e = launch_fused(a, c->tuning.tile_waves, c->tuning.chunk_digis, grid, s))) return e;
@@ -749,7 +750,7 @@ sc_status sc_create(const sc_calib* cal, const sc_options* opt_in, sc_ctx** out)
         return fail(nullptr, SC_ERR_DEVICE, "hipGetDeviceProperties");
     c->n_cu = prop.multiProcessorCount;
     c->device_name = prop.gcnArchName;
-    c->tuning = sc_tuning{3072, 1, 32, 1, 1};
+    c->tuning = sc_tuning{3072, 2, 32, 1, 1};
     load_tuning(c.get());
     if (opt.stream) {
         c->stream = static_cast<hipStream_t>(opt.stream);
@@ -880,7 +881,7 @@ sc_status sc_cluster(sc_ctx* c, const uint8_t* adc_dense, sc_mem in_mem, sc_clus
     if (s0 != SC_OK) return s0;
     SC_HIP(c, hipMemcpyAsync(ws.desc.p, ws.h_desc.p, sizeof(EventDesc), hipMemcpyHostToDevice, c->stream));
     FusedArgs a = fused_args(c, ws, 1);
-    SC_HIP(c, launch_reset(a, c->n_fed, c->stream));
+    SC_HIP(c, launch_reset(a, c->n_fed * c->tuning.tile_waves, c->stream));
     SC_HIP(c, hipEventRecord(c->ev0, c->stream));
     SC_HIP(c, launch_cluster_dense(d_in, a, c->tuning.tile_waves, c->tuning.chunk_digis,
                                    grid_for(c, c->n_fed, true), c->stream));
@@ -1013,7 +1014,8 @@ sc_status sc_set_tuning(sc_ctx* c, const sc_tuning* t) {
     if (!tile_shape_supported(t->tile_waves, t->chunk_digis) || t->tiles_per_cu < 1 ||
         t->tiles_per_cu > 32)
         return fail(c, SC_ERR_INVALID_ARG,
-                    "unsupported tuning (tile_waves must be 1; chunk_digis 1024, 2048, 3072 or 4096)");
+                    "unsupported tuning (tile_waves 1, 2 or 4; chunk_digis 2048, 3072 or 4096, "
+                    "or 1024 with one wave)");
     c->tuning = *t;
     c->tuning.fed_major = t->fed_major ? 1 : 0;
     c->tuning.use_graph = t->use_graph ? 1 : 0;
@@ -1059,9 +1061,10 @@ sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best
     }
     const sc_tuning saved = c->tuning;
     std::vector<sc_tuning> cands;
-    for (uint32_t d : {1024u, 2048u, 3072u, 4096u})
-        for (uint32_t fm : {0u, 1u})
-            if (tile_shape_supported(1, d)) cands.push_back(sc_tuning{d, 1, 32, fm, 0});
+    for (uint32_t w : {1u, 2u, 4u})
+        for (uint32_t d : {1024u, 2048u, 3072u, 4096u})
+            for (uint32_t fm : {0u, 1u})
+                if (tile_shape_supported(w, d)) cands.push_back(sc_tuning{d, w, 32, fm, 0});
     std::vector<uint8_t> ref_cl, ref_adc, cur_cl, cur_adc;
     double best_ms = 1e30;
     sc_tuning best_t = saved;

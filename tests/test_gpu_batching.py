@@ -35,14 +35,18 @@ def full():
     ctx.close()
 
 
-def test_full_detector_batch_exact(full):
+@pytest.mark.parametrize("waves,chunk", [(1, 3072), (1, 1024), (2, 2048), (2, 4096), (4, 3072)])
+def test_full_detector_batch_exact(full, waves, chunk):
     cal, evs, refs, ctx = full
-    ctx.tuning = {"use_graph": 0}
-    results, rc, sts, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs])
-    assert rc == sc.SC_OK
-    for i, (res, ref) in enumerate(zip(results, refs)):
-        compare_clusters(res[0], res[1], ref, f"event {i} occ {evs[i].occ:.4f}")
-    ctx.tuning = {"use_graph": 1}
+    before = ctx.tuning
+    ctx.tuning = {"use_graph": 0, "tile_waves": waves, "chunk_digis": chunk}
+    try:
+        results, rc, sts, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs])
+        assert rc == sc.SC_OK
+        for i, (res, ref) in enumerate(zip(results, refs)):
+            compare_clusters(res[0], res[1], ref, f"event {i} occ {evs[i].occ:.4f}")
+    finally:
+        ctx.tuning = before
 
 
 def test_event_alone_equals_event_in_any_batch(full):
@@ -167,7 +171,7 @@ def _edge_event(kind):
 
 @pytest.mark.parametrize("kind", ["all_empty", "zero_length_feds", "full_fed", "alternating_fed",
                                   "multichunk_fits_stage", "garbage"])
-@pytest.mark.parametrize("shape", [(1024, 1), (2048, 1), (4096, 1)])
+@pytest.mark.parametrize("shape", [(1024, 1), (3072, 1), (2048, 2), (4096, 2), (2048, 4)])
 def test_edge_cases(kind, shape):
     zs, fo, noise, gain, bad = _edge_event(kind)
     ref = oracle.process_event(zs, fo, noise, gain, bad)
@@ -252,7 +256,7 @@ def test_autotune_identical_and_cached(full, tmp_path):
     with make_ctx(cal.noise, cal.gain, cal.bad, tune_cache=cache) as ctx:
         devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs[:4]]
         best = ctx.autotune(devs)
-        assert best["chunk_digis"] in (1024, 2048, 3072, 4096) and best["tile_waves"] == 1
+        assert best["chunk_digis"] in (1024, 2048, 3072, 4096) and best["tile_waves"] in (1, 2, 4)
         results, _, _, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs[:2]])
         for r, ref in zip(results, refs[:2]):
             compare_clusters(r[0], r[1], ref, "after autotune")

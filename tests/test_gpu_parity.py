@@ -119,12 +119,17 @@ def test_plain_path_unpack_then_cluster(cfg0):
     compare_clusters(cl, adc, ref, "plain")
 
 
-@pytest.mark.parametrize("chunk", [1024, 2048, 3072, 4096])
+SHAPES = [(1, 1024), (1, 2048), (1, 3072), (1, 4096), (2, 2048), (2, 3072), (2, 4096), (4, 2048),
+          (4, 3072), (4, 4096)]
+
+
+@pytest.mark.parametrize("waves,chunk", SHAPES, ids=[f"w{w}-d{d}" for w, d in SHAPES])
 @pytest.mark.parametrize("fed_major", [0, 1])
-def test_tuning_choices_identical(cfg0, chunk, fed_major):
+def test_tuning_choices_identical(cfg0, waves, chunk, fed_major):
     cfg, cal, evs, ctx = cfg0
     refs = [oracle.process_event(e.zs, e.fed_offset, cal.noise, cal.gain, cal.bad) for e in evs[:3]]
-    ctx.tuning = {"chunk_digis": chunk, "tile_waves": 1, "fed_major": fed_major,
+    before = ctx.tuning
+    ctx.tuning = {"chunk_digis": chunk, "tile_waves": waves, "fed_major": fed_major,
                   "use_graph": 0}
     try:
         results, rc, _, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs[:3]])
@@ -136,13 +141,14 @@ def test_tuning_choices_identical(cfg0, chunk, fed_major):
         ctx.cluster(dense, out)
         compare_clusters(*out.to_numpy()[:2], refs[0], f"dense chunk {chunk}")
     finally:
-        ctx.tuning = {"chunk_digis": 2048, "tile_waves": 1, "fed_major": 1, "use_graph": 1}
+        ctx.tuning = before
 
 
 def test_unsupported_tile_shapes_are_refused(cfg0):
     cfg, cal, evs, ctx = cfg0
     before = ctx.tuning
-    for t in ({"tile_waves": 3}, {"tile_waves": 8}, {"chunk_digis": 1536}, {"chunk_digis": 512}):
+    for t in ({"tile_waves": 3}, {"tile_waves": 8}, {"chunk_digis": 1536}, {"chunk_digis": 512},
+              {"tile_waves": 2, "chunk_digis": 1024}, {"tile_waves": 4, "chunk_digis": 1024}):
         with pytest.raises(sc.ScError):
             ctx.tuning = t
     assert ctx.tuning == before
