@@ -176,6 +176,22 @@ class Event:
         return Event(zs, fo)
 
 
+class Batch:
+    """Events and outputs of one sc_process_events call, marshalled once. Each output's count
+    fields alias the batch's argument array, so the library's counts appear in the outputs."""
+
+    def __init__(self, events, outs):
+        if len(events) != len(outs):
+            raise ValueError("one output per event")
+        self.events, self.outs = list(events), list(outs)
+        self.n = len(self.events)
+        self.c_ev = (ScEvent * self.n)(*[e.c() for e in self.events])
+        self.c_out = (ScClusters * self.n)(*[o.cs for o in self.outs])
+        self.c_st = (ctypes.c_int * self.n)()
+        for i, o in enumerate(self.outs):
+            o.cs = self.c_out[i]
+
+
 class Output:
     """Cluster output buffers of one event (device: torch CUDA tensors; host: numpy)."""
 
@@ -333,6 +349,18 @@ class Context:
             o.cs.n_cl, o.cs.n_adc = c.n_cl, c.n_adc
         self._check(rc, (SC_OK, SC_MALFORMED, SC_ERR_OVERFLOW))
         return rc, list(sts)
+
+    def batch(self, events, outs) -> "Batch":
+        """Marshals events and outputs once for repeated process_batch calls (the outputs then
+        read their counts from the batch's argument array)."""
+        return Batch(events, outs)
+
+    def process_batch(self, b: "Batch"):
+        """process_events on a prepared Batch. Returns (status, per-event statuses)."""
+        self._order()
+        rc = lib().sc_process_events(self._h, b.c_ev, b.n, b.c_out, b.c_st)
+        self._check(rc, (SC_OK, SC_MALFORMED, SC_ERR_OVERFLOW))
+        return rc, list(b.c_st)
 
     def _ready_for_server(self):
         # the server runs on streams of its own: make everything queued so far finish first

@@ -448,6 +448,7 @@ struct OpenRun {
     uint32_t rp;    // run position of its last digi
     float S;        // sequential noise sum (fmaf, left to right)
     uint32_t Q;     // raw ADC sum | seed-seen << 31
+    uint32_t acc;   // the cluster threshold of the run as it stands (valid if it ends here)
 };
 
 // Cluster threshold of a complete run (§2: charge against the cluster threshold).
@@ -482,13 +483,11 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
     pk = lane() == 0u ? open.key : pk;
     const bool cont = act && strip != 0u && pk == pos;
     const bool cont0 = (__ballot(cont) & 1ull) != 0ull;
-    // the run open at the end of the previous step ends before this step: decide it now
-    if (open.key != kNoKey && !cont0) {
-        if (run_accepted(open.Q, open.S, cal.t_cluster)) {
-            dl[open.head] |= kAccBit;   // same word, same value from every lane
-            n_cl += 1;
-            my_adc += lane() == 0u ? open.rp + 1u : 0u;
-        }
+    // the run open at the end of the previous step ends before this step
+    if (open.key != kNoKey && !cont0 && open.acc) {
+        dl[open.head] |= kAccBit;   // same word, same value from every lane
+        n_cl += 1;
+        my_adc += lane() == 0u ? open.rp + 1u : 0u;
     }
     uint32_t lhead;
     const uint32_t lrp = local_run_pos(act, cont, lhead);
@@ -510,10 +509,12 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
         Qs = upd ? ((a + (Qp & 0xffffu)) | ((Qp | Qs) & 0x80000000u)) : Qs;
     }
     if (valid) dl[j] = d | (act ? kActBit : 0u) | (sd ? kSeedBit : 0u) | (cont ? kContBit : 0u);
-    // runs that end inside this step (lane 63's run may go on: it stays open)
+    // runs that end inside this step; lane 63's run may go on, so it stays open with its
+    // threshold decision as it stands
     const bool next_cont = from_next_lane(cont ? 1u : 0u) != 0u;
-    const bool ends = act && !next_cont && lane() != 63u;
-    const bool acc = ends && run_accepted(Qs, S, cal.t_cluster);
+    const bool at_end = act && !next_cont;
+    const bool thr = at_end && run_accepted(Qs, S, cal.t_cluster);
+    const bool acc = thr && lane() != 63u;
     if (acc) {
         dl[j - rp] |= kAccBit;
         my_adc += rp + 1u;
@@ -524,14 +525,15 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
     open.head = base + 63u - open.rp;
     open.S = __uint_as_float(last_lane(__float_as_uint(S)));
     open.Q = last_lane(Qs);
+    open.acc = (uint32_t)(__ballot(thr) >> 63);
 }
 
 // Forming over the digi list dl[0, nd): steps of 64 digis, the loads of kBatch steps in flight.
 __device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const DeviceCalib& cal,
                                           uint32_t fed, uint32_t& n_cl, uint32_t& n_adc) {
-    constexpr int kBatch = 4;
+    constexpr int kBatch = 8;
     gconst<float>* noise = gc(cal.noise) + fed * kStripsPerFed;
-    OpenRun open{kNoKey, 0u, 0u, 0.0f, 0u};
+    OpenRun open{kNoKey, 0u, 0u, 0.0f, 0u, 0u};
     uint32_t ncl = 0, my_adc = 0;
     for (uint32_t b = 0; b < nd; b += kBatch * kWave) {
         uint32_t d[kBatch];
@@ -552,7 +554,7 @@ __device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const Devic
             if (base < nd) form_step(dl, base, nd, d[k], n[k], cal, open, ncl, my_adc);
         }
     }
-    if (open.key != kNoKey && run_accepted(open.Q, open.S, cal.t_cluster)) {
+    if (open.key != kNoKey && open.acc) {
         dl[open.head] |= kAccBit;
         ncl += 1;
         my_adc += lane() == 0u ? open.rp + 1u : 0u;
@@ -569,7 +571,7 @@ struct OpenCluster {
     uint32_t acc;    // acceptance of the run at lane 63 (for the continuing lanes)
     uint32_t rp;     // run position of lane 63's digi
     uint32_t C, M;   // sums of c and strip*c so far
-    uint32_t last;   // digi word of its last digi
+    u32x4 rec;       // its record as it stands (valid if the cluster ends there)
 };
 
 __device__ __forceinline__ u32x4 make_record(uint32_t fed, uint32_t dw, uint32_t rp, uint32_t C,
@@ -590,7 +592,7 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
                                            uint32_t base_cl, uint32_t base_adc) {
     gmut<uint16_t>* adc_out = gm(ev.adc);
     gmut<u32x4>* cl_out = gm(reinterpret_cast<u32x4*>(ev.cl));
-    OpenCluster oc{0u, 0u, 0u, 0u, 0u, 0u};
+    OpenCluster oc{0u, 0u, 0u, 0u, 0u, u32x4{0u, 0u, 0u, 0u}};
     uint32_t rc = base_cl, pa = base_adc;
     for (uint32_t base = 0; base < nd; base += kWave) {
         const uint32_t j = base + lane();
@@ -601,7 +603,7 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         const bool cont0 = (__ballot(cont) & 1ull) != 0ull;
         // the cluster open at the end of the previous step is complete unless lane 0 continues it
         if (oc.open && !cont0) {
-            if (rc < ev.cap_cl) cl_out[rc] = make_record(fed, oc.last, oc.rp, oc.C, oc.M);
+            if (rc < ev.cap_cl) cl_out[rc] = oc.rec;   // same record from every lane
             rc += 1;
         }
         // members: active digis whose run head is accepted
@@ -642,12 +644,17 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
             C = upd ? C + Cp : C;
             M = upd ? M + Mp : M;
         }
+        // records of the clusters ending in this step; lane 63's record as it stands is kept
+        // for the next step, which stores it if the cluster does not go on
         const bool next_cont = from_next_lane(cont ? 1u : 0u) != 0u;
-        const bool ends = member && !next_cont && lane() != 63u;
+        const bool at_end = member && !next_cont;
+        const bool ends = at_end && lane() != 63u;
         const uint64_t eb = __ballot(ends);
+        u32x4 rec = {0u, 0u, 0u, 0u};
+        if (at_end) rec = make_record(fed, d, rp, C, M);
         if (ends) {
             const uint32_t p = rc + popc(eb & mask_lt());
-            if (p < ev.cap_cl) cl_out[p] = make_record(fed, d, rp, C, M);
+            if (p < ev.cap_cl) cl_out[p] = rec;
         }
         rc += popc(eb);
         oc.open = (uint32_t)(mb >> 63);
@@ -655,9 +662,9 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         oc.rp = last_lane(rp);
         oc.C = last_lane(C);
         oc.M = last_lane(M);
-        oc.last = last_lane(d);
+        oc.rec = u32x4{last_lane(rec.x), last_lane(rec.y), last_lane(rec.z), last_lane(rec.w)};
     }
-    if (oc.open && rc < ev.cap_cl) cl_out[rc] = make_record(fed, oc.last, oc.rp, oc.C, oc.M);
+    if (oc.open && rc < ev.cap_cl) cl_out[rc] = oc.rec;
     wave_sync();
 }
 

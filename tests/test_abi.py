@@ -5,6 +5,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 import paper_2101_11489_amd as sc
@@ -87,3 +88,24 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(sc, "_lib", None)
     with pytest.raises(ImportError):
         sc.lib()
+
+
+def test_batch_marshals_once_and_aliases_counts(built):
+    """A prepared batch holds the argument arrays of sc_process_events; each output's count
+    fields are the batch's array entries, so counts the library writes there show in the
+    outputs (host buffers: no GPU needed)."""
+    n_fed = 2
+    evs = [sc.Event(np.arange(10 + i, dtype=np.uint8), np.array([0, 4, 10 + i], np.uint64))
+           for i in range(3)]
+    outs = [sc.Output(5 + i, 7 + i, n_fed, device=False) for i in range(3)]
+    b = sc.Batch(evs, outs)
+    assert b.n == 3
+    for i in range(3):
+        assert b.c_ev[i].zs == evs[i].zs.ctypes.data
+        assert b.c_ev[i].fed_offset == evs[i].fed_offset.ctypes.data
+        assert b.c_ev[i].mem == sc.SC_MEM_HOST
+        assert (b.c_out[i].cap_cl, b.c_out[i].cap_adc) == (5 + i, 7 + i)
+        b.c_out[i].n_cl, b.c_out[i].n_adc = 100 + i, 200 + i   # as the library would
+    assert [(o.n_cl, o.n_adc) for o in outs] == [(100, 200), (101, 201), (102, 202)]
+    with pytest.raises(ValueError):
+        sc.Batch(evs, outs[:2])
