@@ -44,7 +44,7 @@ struct DeviceCalib {
 struct FusedArgs {
     const EventDesc* ev;
     EventResult* res;
-    unsigned long long* tile_state;  // [n_ev * n_fed * tile_waves] look-back words (channel groups)
+    unsigned long long* tile_state;  // [n_ev * n_fed] decoupled look-back words
     uint32_t* queue;                 // tile ticket counter
     DeviceCalib cal;
     uint32_t n_ev;
@@ -54,7 +54,7 @@ struct FusedArgs {
 // Launch helpers (sc_kernels.hip). All enqueue on `stream` and return the launch error.
 hipError_t launch_derive_calib(const float* noise, const float* gain, const uint8_t* bad,
                                uint32_t n_fed, float* noise_out, hipStream_t stream);
-// Clears n_state look-back words (n_ev x n_fed x tile_waves), the queue and the results.
+// Clears n_state look-back words (n_ev x n_fed), the queue and the results.
 hipError_t launch_reset(const FusedArgs& a, uint32_t n_state, hipStream_t stream);
 hipError_t launch_fused(const FusedArgs& a, uint32_t tile_waves, uint32_t chunk_digis,
                         uint32_t grid, hipStream_t stream);

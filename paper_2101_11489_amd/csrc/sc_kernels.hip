@@ -17,9 +17,10 @@
 //    (+inf for unusable strips, which never passes ADC > T*noise); a run is a chain of active
 //    digis on adjacent strips, and the sequential noise sum of each run is carried from lane to
 //    lane with DPP lane shifts, one strip position per iteration, so no lane walks memory;
-//  * each channel group publishes its counts and looks back over the earlier groups of its event,
-//    64 per load (decoupled look-back), for its output offsets; records are written by the lane
-//    of each cluster's last strip, member ADCs (gain-corrected here) one lane per digi.
+//  * the waves exchange their groups' counts in LDS; the tile publishes the FED's counts and looks
+//    back over the earlier FEDs of its event, 64 per load (decoupled look-back), for its output
+//    offsets; records are written by the lane of each cluster's last strip, member ADCs
+//    (gain-corrected here) one lane per digi.
 // No MFMA: nothing here is a dense contraction.
 
 #include <type_traits>
@@ -138,6 +139,7 @@ struct TileSmem {
     uint8_t ch_st[kNch];
     uint8_t chunk_first[W][kNch + 1];
     uint32_t walk[4];             // bad_from, trailing, delta (from wave 0)
+    uint32_t grp_cnt[W + 1][3];   // per group: clusters, member ADCs; [W]: the FED's offsets
 };
 
 // Workgroup barrier (every wave of the tile passes it); a no-op for single-wave tiles.
@@ -668,11 +670,11 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
     wave_sync();
 }
 
-// ---- decoupled look-back over the channel groups of one event -----------------------------
-// Publishes this group's counts and sums those of the groups before it: lane i reads the word
-// of group top-i, so 64 predecessors are inspected per load; only words not yet published are
-// waited for. Only the counts travel through these words, so relaxed atomics suffice. All
-// values steering the loop are uniform.
+// ---- decoupled look-back over the FEDs of one event -----------------------------------------
+// Publishes this FED's counts and sums those of the FEDs before it: lane i reads the word of
+// FED top-i, so 64 predecessors are inspected per load; only words not yet published are waited
+// for. Only the counts travel through these words, so relaxed atomics suffice. All values
+// steering the loop are uniform.
 __device__ __forceinline__ void publish_and_lookback(unsigned long long* row, uint32_t f,
                                                      uint32_t n_cl, uint32_t n_adc,
                                                      uint32_t& ex_cl, uint32_t& ex_adc,
@@ -684,11 +686,11 @@ __device__ __forceinline__ void publish_and_lookback(unsigned long long* row, ui
     } else {
         __hip_atomic_store(&row[f], pack_state(kFlagAgg, n_cl, n_adc), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-        int top = (int)f - 1;   // highest group not yet summed
+        int top = (int)f - 1;   // highest FED not yet summed
         uint32_t spins = 0;
         for (;;) {
             const int k = top - (int)lane();
-            unsigned long long v = pack_state(kFlagIncl, 0u, 0u);   // before group 0: nothing
+            unsigned long long v = pack_state(kFlagIncl, 0u, 0u);   // before FED 0: nothing
             if (k >= 0) v = __hip_atomic_load(&row[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t flag = (uint32_t)(v >> 62);
             const uint64_t incl = __ballot(flag == kFlagIncl);
@@ -702,7 +704,7 @@ __device__ __forceinline__ void publish_and_lookback(unsigned long long* row, ui
             aadc += wave_sum(take ? (uint32_t)(v & 0x7fffffffu) : 0u);
             if (first_incl < first_none) break;      // reached an inclusive word
             top -= (int)n_take;
-            if (first_none < 64u) {                  // group `top` has not published yet
+            if (first_none < 64u) {                  // FED `top` has not published yet
                 if (++spins > kSpinLimit) { e = 1; break; }
                 __builtin_amdgcn_s_sleep(2);
             }
@@ -732,54 +734,88 @@ __device__ __forceinline__ void emit_status(TileSmem<W, DW>& sm, uint32_t c_lo, 
     if (bits) atomicOr(flags_out, bits);   // uniform branch; every lane ORs the same bits
 }
 
-// The cluster stages of one channel group over its chunks (wave-local; shared by the ZS and the
-// dense front ends). build(c0, c1) fills the group's digi list with channels [c0, c1).
+// The cluster stages of one channel group over its chunks (shared by the ZS and the dense front
+// ends). build(c0, c1) fills the group's digi list with channels [c0, c1). The waves of a tile
+// form their groups, exchange their counts in LDS, and wave 0 publishes the FED's counts and
+// looks back over the earlier FEDs of the event; each group's output offset is then the FED's
+// plus the counts of the groups before it. Every wave passes the same two barriers.
 template <int W, int DW, class BuildFn>
 __device__ void cluster_group(const FusedArgs& A, TileSmem<W, DW>& sm, const EventDesc& ev,
                               uint32_t e, uint32_t f, uint32_t w, uint32_t n_chunks,
                               uint32_t total, BuildFn build) {
     const uint32_t n_fed = A.cal.n_fed;
-    unsigned long long* row = A.tile_state + (size_t)e * n_fed * W;
-    const uint32_t grp = f * W + w;   // look-back index of this channel group
+    unsigned long long* row = A.tile_state + (size_t)e * n_fed;
     uint32_t* dl = sm.digi + w * DW;
     const uint8_t* cf = sm.chunk_first[w];
-    uint32_t n_cl = 0, n_adc = 0, ex_cl = 0, ex_adc = 0, err = 0;
+    uint32_t n_cl = 0, n_adc = 0;
+    // counts: one pass over the group (kept for the writes), or over each chunk
     if (n_chunks == 1) {
         build(uni(cf[0]), uni(cf[1]));
         form_pass(dl, total, A.cal, f, n_cl, n_adc);
-        publish_and_lookback(row, grp, n_cl, n_adc, ex_cl, ex_adc, err);
-        write_pass(sm, dl, total, f, ev, ex_cl, ex_adc);
     } else {
-        // counts of every chunk first, then the look-back, then the chunks again with writes
-        for (int pass = 0; pass < 2; ++pass) {
-            uint32_t bc = 0, ba = 0;
-            if (pass == 1) {
-                publish_and_lookback(row, grp, n_cl, n_adc, ex_cl, ex_adc, err);
-                bc = ex_cl;
-                ba = ex_adc;
-            }
-            for (uint32_t ci = 0; ci < n_chunks; ++ci) {
-                const uint32_t c0 = uni(cf[ci]), c1 = uni(cf[ci + 1]);
-                build(c0, c1);
-                const uint32_t nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
-                uint32_t ccl, cadc;
-                form_pass(dl, nd, A.cal, f, ccl, cadc);
-                if (pass == 0) {
-                    n_cl += ccl;
-                    n_adc += cadc;
-                } else {
-                    write_pass(sm, dl, nd, f, ev, bc, ba);
-                    bc += ccl;
-                    ba += cadc;
-                }
-            }
+        for (uint32_t ci = 0; ci < n_chunks; ++ci) {
+            const uint32_t c0 = uni(cf[ci]), c1 = uni(cf[ci + 1]);
+            build(c0, c1);
+            const uint32_t nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
+            uint32_t ccl, cadc;
+            form_pass(dl, nd, A.cal, f, ccl, cadc);
+            n_cl += ccl;
+            n_adc += cadc;
+        }
+    }
+    // the FED's counts and offsets
+    uint32_t f_cl = n_cl, f_adc = n_adc, pre_cl = 0, pre_adc = 0;
+    if constexpr (W > 1) {
+        sm.grp_cnt[w][0] = n_cl;   // uniform values from every lane
+        sm.grp_cnt[w][1] = n_adc;
+        tile_sync();
+        f_cl = 0;
+        f_adc = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < (uint32_t)W; ++i) {
+            const uint32_t c = uni(sm.grp_cnt[i][0]), a = uni(sm.grp_cnt[i][1]);
+            pre_cl += i < w ? c : 0u;
+            pre_adc += i < w ? a : 0u;
+            f_cl += c;
+            f_adc += a;
+        }
+    }
+    uint32_t ex_cl = 0, ex_adc = 0, err = 0;
+    if (w == 0u) publish_and_lookback(row, f, f_cl, f_adc, ex_cl, ex_adc, err);
+    if constexpr (W > 1) {
+        if (w == 0u) {
+            sm.grp_cnt[W][0] = ex_cl;
+            sm.grp_cnt[W][1] = ex_adc;
+            sm.grp_cnt[W][2] = err;
+        }
+        tile_sync();
+        ex_cl = uni(sm.grp_cnt[W][0]);
+        ex_adc = uni(sm.grp_cnt[W][1]);
+        err = uni(sm.grp_cnt[W][2]);
+    }
+    // writes (the chunks again for a chunked group)
+    if (n_chunks == 1) {
+        write_pass(sm, dl, total, f, ev, ex_cl + pre_cl, ex_adc + pre_adc);
+    } else {
+        uint32_t bc = ex_cl + pre_cl, ba = ex_adc + pre_adc;
+        for (uint32_t ci = 0; ci < n_chunks; ++ci) {
+            const uint32_t c0 = uni(cf[ci]), c1 = uni(cf[ci + 1]);
+            build(c0, c1);
+            const uint32_t nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
+            uint32_t ccl, cadc;
+            form_pass(dl, nd, A.cal, f, ccl, cadc);
+            write_pass(sm, dl, nd, f, ev, bc, ba);
+            bc += ccl;
+            ba += cadc;
         }
     }
     // uniform branches; every lane stores the same values
-    if (err) atomicOr(&A.res[e].flags, kResSpinTimeout);
-    if (f == n_fed - 1 && w == W - 1) {
-        A.res[e].n_cl = ex_cl + n_cl;
-        A.res[e].n_adc = ex_adc + n_adc;
+    if (w == 0u) {
+        if (err) atomicOr(&A.res[e].flags, kResSpinTimeout);
+        if (f == n_fed - 1) {
+            A.res[e].n_cl = ex_cl + f_cl;
+            A.res[e].n_adc = ex_adc + f_adc;
+        }
     }
 }
 

@@ -87,8 +87,7 @@ struct Workspace {
         hipError_t e;
         if ((e = desc.ensure(sizeof(EventDesc) * n_ev)) != hipSuccess) return e;
         if ((e = res.ensure(sizeof(EventResult) * n_ev)) != hipSuccess) return e;
-        // one look-back word per channel group: up to 4 groups per FED
-        if ((e = state.ensure(sizeof(unsigned long long) * (size_t)n_ev * n_fed * 4)) != hipSuccess) return e;
+        if ((e = state.ensure(sizeof(unsigned long long) * (size_t)n_ev * n_fed)) != hipSuccess) return e;
         if ((e = queue.ensure(64)) != hipSuccess) return e;
         if ((e = h_desc.ensure(sizeof(EventDesc) * n_ev)) != hipSuccess) return e;
         if ((e = h_res.ensure(sizeof(EventResult) * n_ev)) != hipSuccess) return e;
@@ -337,7 +336,7 @@ hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bo
     if ((e = hipMemcpyAsync(ws.desc.p, ws.h_desc.p, sizeof(EventDesc) * n, hipMemcpyHostToDevice, s)))
         return e;
     const FusedArgs a = fused_args(c, ws, n);
-    if ((e = launch_reset(a, n * c->n_fed * c->tuning.tile_waves, s))) return e;
+    if ((e = launch_reset(a, n * c->n_fed, s))) return e;
     if (timed && (e = hipEventRecord(c->ev0, s))) return e;
     const uint32_t grid = grid_for(c, n * c->n_fed, false);
     if ((e = launch_fused(a, c->tuning.tile_waves, c->tuning.chunk_digis, grid, s))) return e;
@@ -881,7 +880,7 @@ sc_status sc_cluster(sc_ctx* c, const uint8_t* adc_dense, sc_mem in_mem, sc_clus
     if (s0 != SC_OK) return s0;
     SC_HIP(c, hipMemcpyAsync(ws.desc.p, ws.h_desc.p, sizeof(EventDesc), hipMemcpyHostToDevice, c->stream));
     FusedArgs a = fused_args(c, ws, 1);
-    SC_HIP(c, launch_reset(a, c->n_fed * c->tuning.tile_waves, c->stream));
+    SC_HIP(c, launch_reset(a, c->n_fed, c->stream));
     SC_HIP(c, hipEventRecord(c->ev0, c->stream));
     SC_HIP(c, launch_cluster_dense(d_in, a, c->tuning.tile_waves, c->tuning.chunk_digis,
                                    grid_for(c, c->n_fed, true), c->stream));
