@@ -72,6 +72,41 @@ __device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);
 }
 
+// Sums along the runs of a 64-digi step: lane i adds the values of the r lanes just below it
+// (the part of its run that lies in the step; r = 0 outside runs), whatever the run lengths, in
+// six DPP steps: Hillis-Steele inside rows of 16 lanes (row_shr 1, 2, 4, 8; lanes whose source
+// lies in the row before read 0), then the carries across rows (row_bcast:15 into rows 1 and 3,
+// row_bcast:31 into rows 2 and 3), each taken only by lanes whose run began before the row.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint32_t dpp_in(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, RowMask, 0xf, true);
+}
+__device__ __forceinline__ uint32_t as_bits(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ uint32_t as_bits(uint32_t x) { return x; }
+__device__ __forceinline__ void add_if(float& x, uint32_t y, bool c) {
+    x = c ? x + __uint_as_float(y) : x;
+}
+__device__ __forceinline__ void add_if(uint32_t& x, uint32_t y, bool c) { x = c ? x + y : x; }
+
+template <int Ctrl, int RowMask, class A, class B>
+__device__ __forceinline__ void run_sum_step(A& a, B& b, bool c) {
+    const uint32_t ya = dpp_in<Ctrl, RowMask>(as_bits(a));
+    const uint32_t yb = dpp_in<Ctrl, RowMask>(as_bits(b));
+    add_if(a, ya, c);
+    add_if(b, yb, c);
+}
+
+template <class A, class B>
+__device__ __forceinline__ void run_sums(A& a, B& b, uint32_t r) {
+    const uint32_t l = lane(), lr = l & 15u;
+    run_sum_step<0x111, 0xf>(a, b, r >= 1u);
+    run_sum_step<0x112, 0xf>(a, b, r >= 2u);
+    run_sum_step<0x114, 0xf>(a, b, r >= 4u);
+    run_sum_step<0x118, 0xf>(a, b, r >= 8u);
+    run_sum_step<0x142, 0xa>(a, b, (l & 16u) != 0u && r > lr);
+    run_sum_step<0x143, 0xc>(a, b, l >= 32u && r + 32u > l);
+}
+
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t& total) {
     uint32_t x = v;
 #pragma unroll
@@ -116,10 +151,10 @@ __device__ __forceinline__ unsigned long long pack_state(uint64_t flag, uint32_t
 }
 
 // Digi word in the list: adc(8) | strip(8) | channel-in-FED(7), and after forming the flags
-// active | seed | continues-previous | accepted (the accepted bit on the first digi of an
-// accepted run).
+// active | seed | continues-previous | accepted | undecided (the last two on the first digi of a
+// run: accepted, or left to the sequential noise sum).
 constexpr uint32_t kActBit = 1u << 23, kSeedBit = 1u << 24, kContBit = 1u << 25,
-                   kAccBit = 1u << 26;
+                   kAccBit = 1u << 26, kRedoBit = 1u << 27;
 constexpr uint32_t kNoKey = 0xffffffffu;
 __device__ __forceinline__ uint32_t d_adc(uint32_t d) { return d & 255u; }
 __device__ __forceinline__ uint32_t d_strip(uint32_t d) { return (d >> 8) & 255u; }
@@ -448,14 +483,58 @@ struct OpenRun {
     uint32_t key;   // position + 1 of its last digi (kNoKey: no open run)
     uint32_t head;  // digi index of its first digi
     uint32_t rp;    // run position of its last digi
-    float S;        // sequential noise sum (fmaf, left to right)
-    uint32_t Q;     // raw ADC sum | seed-seen << 31
-    uint32_t acc;   // the cluster threshold of the run as it stands (valid if it ends here)
+    float S;        // noise sum so far in tree order (steers the cluster-threshold filter)
+    uint32_t Q;     // raw ADC sum | seed count << 16
+    uint32_t mark;  // its threshold decision as it stands (valid if it ends here): a head bit
 };
 
-// Cluster threshold of a complete run (§2: charge against the cluster threshold).
-__device__ __forceinline__ bool run_accepted(uint32_t Qs, float S, float t_cluster) {
-    return (Qs >> 31) != 0u && (float)(Qs & 0xffffu) >= t_cluster * __builtin_sqrtf(S);
+// Cluster threshold of the runs ending at their lanes (§2: charge against the cluster
+// threshold): accepted when seeded and (float)Q >= t * sqrtf(S), S summed by fmaf from the run's
+// first strip. St, the same sum taken in tree order by run_sums, is within (L + 35) roundings of
+// the exact sum, as the sequential one is within L (L = rp + 1 strips; every path through the
+// tree has at most 35 additions and products for a run of at most 256 strips). So wherever
+// q >= r (1 + e) or q < r (1 - e), with r = t * sqrt(St) and e = (L + 64) * 2^-24, the
+// sequential sum decides the same way. Returns the head bit: kAccBit (accepted), kRedoBit (too
+// close to call: settle_runs decides from the sequential sum) or 0.
+__device__ __forceinline__ uint32_t cluster_mark(bool end, uint32_t rp, uint32_t Q, float St,
+                                                 float t) {
+    const bool seeded = end && (Q >> 16) != 0u;
+    const float q = (float)(Q & 0xffffu);
+    const float r = t * __builtin_amdgcn_sqrtf(St);
+    const float e = (float)(rp + 65u) * 0x1p-24f;
+    const bool in_range = St >= 0x1p-60f && St <= 0x1p100f;   // false for NaN
+    const bool yes = in_range && q >= r * (1.0f + e);
+    const bool no = in_range && q < r * (1.0f - e);
+    return !seeded ? 0u : yes ? kAccBit : no ? 0u : kRedoBit;
+}
+
+// The runs marked kRedoBit in dl[0, nd): their threshold from the sequential fmaf sum of the
+// noise squares from the first strip, as the definition has it (rare; one lane per run).
+__device__ void settle_runs(uint32_t* dl, uint32_t nd, gconst<float>* noise, float t,
+                            uint32_t& n_cl, uint32_t& my_adc) {
+    for (uint32_t base = 0; base < nd; base += kWave) {
+        const uint32_t j = base + lane();
+        const uint32_t d = j < nd ? dl[j] : 0u;
+        bool acc = false;
+        uint32_t width = 0;
+        if (d & kRedoBit) {
+            float S = 0.0f;
+            uint32_t Q = 0, i = j, w = d;
+            for (;;) {
+                const float ni = noise[d_pos(w)];
+                S = __builtin_fmaf(ni, ni, S);
+                Q += d_adc(w);
+                if (++i >= nd) break;
+                w = dl[i];
+                if (!(w & kContBit)) break;
+            }
+            width = i - j;
+            acc = (float)Q >= t * __builtin_sqrtf(S);
+            if (acc) dl[j] = d | kAccBit;
+        }
+        if (acc) my_adc += width;
+        n_cl += popc(__ballot(acc));
+    }
 }
 
 // Local run position of each lane's digi in a step: distance to the nearest run head at or below
@@ -472,7 +551,7 @@ __device__ __forceinline__ uint32_t local_run_pos(bool act, bool cont, uint32_t&
 // accepted run heads and counts clusters / member ADCs.
 __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t nd, uint32_t d,
                                           float n, const DeviceCalib& cal, OpenRun& open,
-                                          uint32_t& n_cl, uint32_t& my_adc) {
+                                          uint32_t& n_cl, uint32_t& my_adc, uint32_t& pending) {
     const uint32_t j = base + lane();
     const bool valid = j < nd;
     const uint32_t a = d_adc(d), strip = d_strip(d), pos = d_pos(d);
@@ -486,48 +565,46 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
     const bool cont = act && strip != 0u && pk == pos;
     const bool cont0 = (__ballot(cont) & 1ull) != 0ull;
     // the run open at the end of the previous step ends before this step
-    if (open.key != kNoKey && !cont0 && open.acc) {
-        dl[open.head] |= kAccBit;   // same word, same value from every lane
-        n_cl += 1;
-        my_adc += lane() == 0u ? open.rp + 1u : 0u;
+    if (open.key != kNoKey && !cont0 && open.mark) {
+        dl[open.head] |= open.mark;   // same word, same value from every lane
+        if (open.mark == kAccBit) {
+            n_cl += 1;
+            my_adc += lane() == 0u ? open.rp + 1u : 0u;
+        } else {
+            pending += 1;
+        }
     }
     uint32_t lhead;
     const uint32_t lrp = local_run_pos(act, cont, lhead);
     const bool from_open = cont0 && lhead == 0u;   // my run began in an earlier step
     const uint32_t rp = lrp + ((act && from_open) ? open.rp + 1u : 0u);
-    // sums along the run: S by sequential fmaf from the left strip, raw charge, seed seen
-    float S = __builtin_fmaf(n, n, 0.0f);
-    uint32_t Qs = a | (sd ? 0x80000000u : 0u);
+    // sums along the run: noise squares (tree order), raw charge, seeds
+    float S = act ? n * n : 0.0f;
+    uint32_t Q = act ? a + (sd ? 0x10000u : 0u) : 0u;
     if (cont0) {
         const bool l0 = lane() == 0u;
-        S = l0 ? __builtin_fmaf(n, n, open.S) : S;
-        Qs = l0 ? ((a + (open.Q & 0xffffu)) | ((open.Q | Qs) & 0x80000000u)) : Qs;
+        S = l0 ? S + open.S : S;
+        Q = l0 ? Q + open.Q : Q;
     }
-    for (uint32_t k = 1; __ballot(lrp >= k) != 0ull; ++k) {
-        const float Sp = __uint_as_float(from_prev_lane(__float_as_uint(S)));
-        const uint32_t Qp = from_prev_lane(Qs);
-        const bool upd = lrp == k;
-        S = upd ? __builtin_fmaf(n, n, Sp) : S;
-        Qs = upd ? ((a + (Qp & 0xffffu)) | ((Qp | Qs) & 0x80000000u)) : Qs;
-    }
+    run_sums(S, Q, lrp);
     if (valid) dl[j] = d | (act ? kActBit : 0u) | (sd ? kSeedBit : 0u) | (cont ? kContBit : 0u);
     // runs that end inside this step; lane 63's run may go on, so it stays open with its
     // threshold decision as it stands
     const bool next_cont = from_next_lane(cont ? 1u : 0u) != 0u;
     const bool at_end = act && !next_cont;
-    const bool thr = at_end && run_accepted(Qs, S, cal.t_cluster);
-    const bool acc = thr && lane() != 63u;
-    if (acc) {
-        dl[j - rp] |= kAccBit;
-        my_adc += rp + 1u;
-    }
+    const uint32_t mark = cluster_mark(at_end, rp, Q, S, cal.t_cluster);
+    const bool ends = mark != 0u && lane() != 63u;
+    if (ends) dl[j - rp] |= mark;
+    const bool acc = ends && mark == kAccBit;
+    if (acc) my_adc += rp + 1u;
     n_cl += popc(__ballot(acc));
+    pending += popc(__ballot(ends && mark == kRedoBit));
     open.key = last_lane(key);
     open.rp = last_lane(rp);
     open.head = base + 63u - open.rp;
     open.S = __uint_as_float(last_lane(__float_as_uint(S)));
-    open.Q = last_lane(Qs);
-    open.acc = (uint32_t)(__ballot(thr) >> 63);
+    open.Q = last_lane(Q);
+    open.mark = last_lane(mark);
 }
 
 // Forming over the digi list dl[0, nd): steps of 64 digis, the loads of kBatch steps in flight.
@@ -536,7 +613,7 @@ __device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const Devic
     constexpr int kBatch = 8;
     gconst<float>* noise = gc(cal.noise) + fed * kStripsPerFed;
     OpenRun open{kNoKey, 0u, 0u, 0.0f, 0u, 0u};
-    uint32_t ncl = 0, my_adc = 0;
+    uint32_t ncl = 0, my_adc = 0, pending = 0;
     for (uint32_t b = 0; b < nd; b += kBatch * kWave) {
         uint32_t d[kBatch];
         float n[kBatch];
@@ -553,13 +630,22 @@ __device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const Devic
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
             const uint32_t base = b + (uint32_t)(k * kWave);
-            if (base < nd) form_step(dl, base, nd, d[k], n[k], cal, open, ncl, my_adc);
+            if (base < nd)
+                form_step(dl, base, nd, d[k], n[k], cal, open, ncl, my_adc, pending);
         }
     }
-    if (open.key != kNoKey && open.acc) {
-        dl[open.head] |= kAccBit;
-        ncl += 1;
-        my_adc += lane() == 0u ? open.rp + 1u : 0u;
+    if (open.key != kNoKey && open.mark) {
+        dl[open.head] |= open.mark;
+        if (open.mark == kAccBit) {
+            ncl += 1;
+            my_adc += lane() == 0u ? open.rp + 1u : 0u;
+        } else {
+            pending += 1;
+        }
+    }
+    if (pending) {
+        wave_sync();
+        settle_runs(dl, nd, noise, cal.t_cluster, ncl, my_adc);
     }
     n_cl = ncl;
     n_adc = wave_sum(my_adc);
@@ -640,12 +726,7 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
             C = l0 ? C + oc.C : C;
             M = l0 ? M + oc.M : M;
         }
-        for (uint32_t k = 1; __ballot(lrp >= k) != 0ull; ++k) {
-            const uint32_t Cp = from_prev_lane(C), Mp = from_prev_lane(M);
-            const bool upd = lrp == k;
-            C = upd ? C + Cp : C;
-            M = upd ? M + Mp : M;
-        }
+        run_sums(C, M, lrp);
         // records of the clusters ending in this step; lane 63's record as it stands is kept
         // for the next step, which stores it if the cluster does not go on
         const bool next_cont = from_next_lane(cont ? 1u : 0u) != 0u;

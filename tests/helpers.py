@@ -130,3 +130,67 @@ def golden_calib(case: dict, n_fed: int):
     for ch, s in case.get("bad", []):
         bad[ch * NS + s] = 1
     return noise, gain, bad
+
+
+# ---- runs at the cluster threshold -----------------------------------------------------------
+
+def sqrt_f32(x: np.float32) -> np.float32:
+    """Correctly rounded binary32 square root (numpy's float32 sqrt is IEEE)."""
+    return np.sqrt(np.float32(x), dtype=np.float32)
+
+
+def noise_sum(noises, s=np.float32(0.0)) -> np.float32:
+    """Sequential fmaf sum of the noise squares from the first strip, exact binary32 rounding."""
+    for n in noises:
+        s = fmaf_exact(np.float32(n), np.float32(n), s)
+    return s
+
+
+def bound_of(s: np.float32, t: float) -> np.float32:
+    """fl(t * sqrtf(S)): the right-hand side of the cluster threshold."""
+    return np.float32(np.float32(t) * sqrt_f32(s))
+
+
+def threshold_runs(seed: int, t_cluster=5.0, lengths=(1, 2, 3, 4, 5, 7, 9, 15, 31, 33, 63, 64,
+                                                       65, 66, 100, 129, 200, 250)):
+    """One FED of runs whose charge sits at the cluster threshold: for each run the charge Q (sum
+    of its ADCs) equals fl(t * sqrtf(S)) exactly, or lies one binary32 step above or below it
+    (S: sequential fmaf sum of the noise squares). Noise is proportional to the ADC (n = c * a with
+    c <= sqrt(L) / t < 3.2), so every strip is active and a seed for thresholds t_channel = 0.25,
+    t_seed = 0.3; the last strip's noise is stepped ulp by ulp towards the wanted bound. Returns
+    ({channel: [(first, adcs)]}, noise, runs) with runs as tuples (channel, first, length, Q,
+    bound)."""
+    rng = np.random.default_rng(seed)
+    noise, _, _ = calib_arrays(1)
+    chan_runs, runs = {}, []
+    k = 0
+    for ch in range(NCH):
+        pos = 0
+        while True:
+            L = int(lengths[rng.integers(len(lengths))])
+            if pos + L > NS:
+                break
+            adcs = [int(v) for v in rng.integers(1, 31, size=L)]
+            q = sum(adcs)
+            c = q / (t_cluster * float(np.sqrt(np.sum(np.square(adcs, dtype=np.float64)))))
+            ns = [np.float32(c * a) for a in adcs]
+            s_prev = noise_sum(ns[:-1])
+            want = (np.float32(q) if k % 3 == 0 else
+                    np.nextafter(np.float32(q), np.float32(np.inf if k % 3 == 1 else -np.inf)))
+            best, best_d = None, None
+            n_last = ns[-1]
+            for _ in range(64):
+                r = bound_of(fmaf_exact(n_last, n_last, s_prev), t_cluster)
+                d = float(r) - float(want)
+                if best_d is None or abs(d) < abs(best_d):
+                    best, best_d = n_last, d
+                if d == 0:
+                    break
+                n_last = np.nextafter(n_last, np.float32(-np.inf if d > 0 else np.inf))
+            ns[-1] = best
+            noise[ch * NS + pos: ch * NS + pos + L] = ns
+            chan_runs.setdefault(ch, []).append((pos, adcs))
+            runs.append((ch, pos, L, q, bound_of(fmaf_exact(best, best, s_prev), t_cluster)))
+            k += 1
+            pos += L + 1
+    return chan_runs, noise, runs

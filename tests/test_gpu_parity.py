@@ -11,7 +11,8 @@ import pytest
 
 import fedgen
 import oracle
-from helpers import golden_calib, golden_event, parse_channel_set, NS
+from helpers import (calib_arrays, event_from_runs, golden_calib, golden_event,
+                     parse_channel_set, threshold_runs, NS)
 
 pytestmark = pytest.mark.gpu
 
@@ -93,6 +94,24 @@ def test_cluster_dense_hand_channels():
                 cl, adc, _ = out.to_numpy()
                 compare_clusters(cl, adc, ref, case["name"])
                 assert rc == sc.SC_OK
+
+
+@pytest.mark.parametrize("waves,chunk", [(1, 1024), (2, 3072), (4, 2048)])
+def test_runs_at_the_cluster_threshold(waves, chunk):
+    # charges equal to fl(t * sqrtf(S)) or one binary32 step beside it, runs of 1 to 250 strips
+    # (across 64-digi steps): decisions the kernels cannot take from their tree-order noise sum
+    thr = dict(t_seed=0.3, t_channel=0.25, t_cluster=5.0)
+    for seed in (1, 2):
+        chan_runs, noise, runs = threshold_runs(seed)
+        _, gain, bad = calib_arrays(1)
+        zs, fo = event_from_runs(chan_runs)
+        ref = oracle.process_event(zs, fo, noise, gain, bad, **thr)
+        with make_ctx(noise, gain, bad, **thr) as ctx:
+            ctx.tuning = {"chunk_digis": chunk, "tile_waves": waves, "use_graph": 0}
+            (res,), rc, _, _ = run_fused(ctx, [(zs, fo)])
+            assert rc == sc.SC_OK
+            compare_clusters(res[0], res[1], ref, f"seed {seed}")
+            assert bary_bit_exact(res[0], ref)
 
 
 def test_generated_config0_batch(cfg0):

@@ -17,7 +17,7 @@ import pytest
 import fedgen
 import oracle
 from helpers import (NS, calib_arrays, event_from_runs, golden_calib, golden_event,
-                     parse_channel_set, round_f32, fmaf_exact)
+                     parse_channel_set, round_f32, fmaf_exact, threshold_runs)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_channels.json")
 CASES = json.load(open(GOLDEN))["cases"]
@@ -104,6 +104,27 @@ def test_cluster_threshold_exact_square_roots():
     zs, fo = event_from_runs({0: [(0, [4] + [3] * 8)]})
     out = oracle.process_event(zs, fo, noise1, gain, bad)
     assert out.cl.size == 1 and out.cl["width"][0] == 9
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_cluster_threshold_at_the_bound(seed):
+    # Runs whose charge equals fl(t * sqrtf(S)) or lies one binary32 step beside it, S the
+    # sequential fmaf sum, worked out in exact rational arithmetic: a different summation order,
+    # a separately rounded product, or > in place of >= flips some of these decisions.
+    chan_runs, noise, runs = threshold_runs(seed)
+    _, gain, bad = calib_arrays(1)
+    zs, fo = event_from_runs(chan_runs)
+    out = oracle.process_event(zs, fo, noise, gain, bad, t_seed=0.3, t_channel=0.25, t_cluster=5.0)
+    for ch, first, L, q, bound in runs:      # every strip active and a seed by construction
+        a = np.array(chan_runs[ch][[r[0] for r in chan_runs[ch]].index(first)][1], np.float32)
+        n = noise[ch * NS + first: ch * NS + first + L]
+        assert np.all(a > np.float32(0.25) * n) and np.all(a > np.float32(0.3) * n)
+    exp = [(ch, first, L, q) for ch, first, L, q, bound in runs if np.float32(q) >= bound]
+    got = [tuple(int(v) for v in r) for r in out.cl[["channel", "first", "width", "charge"]]]
+    assert got == exp
+    n_tie = sum(1 for *_, q, b in runs if np.float32(q) == b)
+    n_rej = sum(1 for *_, q, b in runs if np.float32(q) < b)
+    assert n_tie > 50 and n_rej > 50 and len(exp) > n_tie
 
 
 def test_gain_rounding_ties_to_even():

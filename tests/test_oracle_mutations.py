@@ -23,6 +23,12 @@ MUTANTS = {
                                  "(float)q_raw > t_cluster * sqrtf(sum_n2)"),
     "noise_not_squared": ("sum_n2 = fmaf(nz[i], nz[i], sum_n2);", "sum_n2 += nz[i];"),
     "no_sqrt": ("t_cluster * sqrtf(sum_n2)", "t_cluster * sum_n2"),
+    "noise_sum_rounds_product": ("sum_n2 = fmaf(nz[i], nz[i], sum_n2);",
+                                 "sum_n2 = sum_n2 + nz[i] * nz[i];"),
+    "noise_sum_right_to_left": ("sum_n2 = fmaf(nz[i], nz[i], sum_n2);",
+                                "sum_n2 = fmaf(nz[r + l - i], nz[r + l - i], sum_n2);"),
+    "threshold_in_double": ("(float)q_raw >= t_cluster * sqrtf(sum_n2)",
+                            "(double)q_raw >= (double)t_cluster * sqrt((double)sum_n2)"),
     "gain_wrong_apv": ("rintf((float)a[i] / g[i / NAPV])", "rintf((float)a[i] / g[0])"),
     "gain_multiplies": ("rintf((float)a[i] / g[i / NAPV])", "rintf((float)a[i] * g[i / NAPV])"),
     "gain_truncates": ("rintf((float)a[i] / g[i / NAPV])", "truncf((float)a[i] / g[i / NAPV])"),
