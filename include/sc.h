@@ -138,7 +138,7 @@ typedef struct {
 
 /* Performance-relevant choices of the fused kernel (found by sc_autotune). */
 typedef struct {
-    uint32_t chunk_digis;    /* digis a tile holds in LDS per pass: 2048, 3072, 4096; 1024 with 1 wave */
+    uint32_t chunk_digis;    /* digis a tile holds in LDS per pass: 2048, 3072, 4096; 1024 with 1 wave, 2880 with 2 */
     uint32_t tile_waves;     /* wavefronts per tile: 1, 2 or 4 (each takes 96/W channels) */
     uint32_t tiles_per_cu;   /* cap on resident tiles per compute unit (persistent grid), 1..32 */
     uint32_t fed_major;      /* 1: tiles ordered FED-major (calibration reuse), 0: event-major */

@@ -163,7 +163,7 @@ __device__ __forceinline__ uint32_t d_pos(uint32_t d) { return (d >> 8) & 0x7fff
 
 template <int W, int DW>
 struct TileSmem {
-    static constexpr int kStageBytes = 8192;
+    static constexpr int kStageBytes = 6656;   // a FED of full-detector events at 5 % occupancy
     static constexpr int kStageData = kStageBytes - 16;   // FED bytes that fit (alignment slack)
     alignas(16) uint8_t stage[kStageBytes];              // the FED's bytes
     uint32_t digi[W * DW];                               // wave w: [w*DW, (w+1)*DW)
@@ -176,6 +176,9 @@ struct TileSmem {
     uint32_t walk[4];             // bad_from, trailing, delta (from wave 0)
     uint32_t grp_cnt[W + 1][3];   // per group: clusters, member ADCs; [W]: the FED's offsets
 };
+
+// Two-wave tiles of 2880 digis fit eight to a CU (160 KiB of LDS).
+static_assert(sizeof(TileSmem<2, 1440>) <= 160 * 1024 / 8, "eight two-wave tiles per CU");
 
 // Workgroup barrier (every wave of the tile passes it); a no-op for single-wave tiles.
 __device__ __forceinline__ void tile_sync() { __syncthreads(); }
@@ -210,7 +213,7 @@ template <int NT, int W, int DW>
 __device__ __forceinline__ uint32_t stage_bytes(TileSmem<W, DW>& sm, uint32_t t,
                                                 const uint8_t* gsrc, uint32_t n,
                                                 const float* gains) {
-    constexpr int K = TileSmem<W, DW>::kStageBytes / (16 * NT);
+    constexpr int K = (TileSmem<W, DW>::kStageBytes + 16 * NT - 1) / (16 * NT);
     const uintptr_t a = reinterpret_cast<uintptr_t>(gsrc);
     const uintptr_t a0 = a & ~uintptr_t(15);
     const uint32_t delta = (uint32_t)(a - a0);
@@ -1125,7 +1128,7 @@ bool dispatch(uint32_t w, uint32_t d, F&& f) {
 #define SC_CASE(WW, DD) \
     if (w == WW && d == DD) { f(std::integral_constant<int, WW>{}, std::integral_constant<int, DD / WW>{}); return true; }
     SC_CASE(1, 1024) SC_CASE(1, 2048) SC_CASE(1, 3072) SC_CASE(1, 4096)
-    SC_CASE(2, 2048) SC_CASE(2, 3072) SC_CASE(2, 4096)
+    SC_CASE(2, 2048) SC_CASE(2, 2880) SC_CASE(2, 3072) SC_CASE(2, 4096)
     SC_CASE(4, 2048) SC_CASE(4, 3072) SC_CASE(4, 4096)
 #undef SC_CASE
     return false;

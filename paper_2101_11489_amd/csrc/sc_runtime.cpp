@@ -749,7 +749,7 @@ sc_status sc_create(const sc_calib* cal, const sc_options* opt_in, sc_ctx** out)
         return fail(nullptr, SC_ERR_DEVICE, "hipGetDeviceProperties");
     c->n_cu = prop.multiProcessorCount;
     c->device_name = prop.gcnArchName;
-    c->tuning = sc_tuning{3072, 2, 32, 1, 1};
+    c->tuning = sc_tuning{2880, 2, 32, 1, 1};
     load_tuning(c.get());
     if (opt.stream) {
         c->stream = static_cast<hipStream_t>(opt.stream);
@@ -1014,7 +1014,7 @@ sc_status sc_set_tuning(sc_ctx* c, const sc_tuning* t) {
         t->tiles_per_cu > 32)
         return fail(c, SC_ERR_INVALID_ARG,
                     "unsupported tuning (tile_waves 1, 2 or 4; chunk_digis 2048, 3072 or 4096, "
-                    "or 1024 with one wave)");
+                    "1024 with one wave, 2880 with two)");
     c->tuning = *t;
     c->tuning.fed_major = t->fed_major ? 1 : 0;
     c->tuning.use_graph = t->use_graph ? 1 : 0;
@@ -1061,7 +1061,7 @@ sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best
     const sc_tuning saved = c->tuning;
     std::vector<sc_tuning> cands;
     for (uint32_t w : {1u, 2u, 4u})
-        for (uint32_t d : {1024u, 2048u, 3072u, 4096u})
+        for (uint32_t d : {1024u, 2048u, 2880u, 3072u, 4096u})
             for (uint32_t fm : {0u, 1u})
                 if (tile_shape_supported(w, d)) cands.push_back(sc_tuning{d, w, 32, fm, 0});
     std::vector<uint8_t> ref_cl, ref_adc, cur_cl, cur_adc;

@@ -35,7 +35,8 @@ def full():
     ctx.close()
 
 
-@pytest.mark.parametrize("waves,chunk", [(1, 3072), (1, 1024), (2, 2048), (2, 4096), (4, 3072)])
+@pytest.mark.parametrize("waves,chunk", [(1, 3072), (1, 1024), (2, 2048), (2, 2880), (2, 4096),
+                                         (4, 3072)])
 def test_full_detector_batch_exact(full, waves, chunk):
     cal, evs, refs, ctx = full
     before = ctx.tuning
@@ -171,7 +172,7 @@ def _edge_event(kind):
 
 @pytest.mark.parametrize("kind", ["all_empty", "zero_length_feds", "full_fed", "alternating_fed",
                                   "multichunk_fits_stage", "garbage"])
-@pytest.mark.parametrize("shape", [(1024, 1), (3072, 1), (2048, 2), (4096, 2), (2048, 4)])
+@pytest.mark.parametrize("shape", [(1024, 1), (3072, 1), (2048, 2), (2880, 2), (4096, 2), (2048, 4)])
 def test_edge_cases(kind, shape):
     zs, fo, noise, gain, bad = _edge_event(kind)
     ref = oracle.process_event(zs, fo, noise, gain, bad)
@@ -256,7 +257,7 @@ def test_autotune_identical_and_cached(full, tmp_path):
     with make_ctx(cal.noise, cal.gain, cal.bad, tune_cache=cache) as ctx:
         devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs[:4]]
         best = ctx.autotune(devs)
-        assert best["chunk_digis"] in (1024, 2048, 3072, 4096) and best["tile_waves"] in (1, 2, 4)
+        assert best["chunk_digis"] in (1024, 2048, 2880, 3072, 4096) and best["tile_waves"] in (1, 2, 4)
         results, _, _, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs[:2]])
         for r, ref in zip(results, refs[:2]):
             compare_clusters(r[0], r[1], ref, "after autotune")

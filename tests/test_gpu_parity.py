@@ -96,7 +96,7 @@ def test_cluster_dense_hand_channels():
                 assert rc == sc.SC_OK
 
 
-@pytest.mark.parametrize("waves,chunk", [(1, 1024), (2, 3072), (4, 2048)])
+@pytest.mark.parametrize("waves,chunk", [(1, 1024), (2, 2880), (2, 3072), (4, 2048)])
 def test_runs_at_the_cluster_threshold(waves, chunk):
     # charges equal to fl(t * sqrtf(S)) or one binary32 step beside it, runs of 1 to 250 strips
     # (across 64-digi steps): decisions the kernels cannot take from their tree-order noise sum
@@ -138,8 +138,8 @@ def test_plain_path_unpack_then_cluster(cfg0):
     compare_clusters(cl, adc, ref, "plain")
 
 
-SHAPES = [(1, 1024), (1, 2048), (1, 3072), (1, 4096), (2, 2048), (2, 3072), (2, 4096), (4, 2048),
-          (4, 3072), (4, 4096)]
+SHAPES = [(1, 1024), (1, 2048), (1, 3072), (1, 4096), (2, 2048), (2, 2880), (2, 3072), (2, 4096),
+          (4, 2048), (4, 3072), (4, 4096)]
 
 
 @pytest.mark.parametrize("waves,chunk", SHAPES, ids=[f"w{w}-d{d}" for w, d in SHAPES])
@@ -167,7 +167,8 @@ def test_unsupported_tile_shapes_are_refused(cfg0):
     cfg, cal, evs, ctx = cfg0
     before = ctx.tuning
     for t in ({"tile_waves": 3}, {"tile_waves": 8}, {"chunk_digis": 1536}, {"chunk_digis": 512},
-              {"tile_waves": 2, "chunk_digis": 1024}, {"tile_waves": 4, "chunk_digis": 1024}):
+              {"tile_waves": 2, "chunk_digis": 1024}, {"tile_waves": 4, "chunk_digis": 1024},
+              {"tile_waves": 1, "chunk_digis": 2880}, {"tile_waves": 4, "chunk_digis": 2880}):
         with pytest.raises(sc.ScError):
             ctx.tuning = t
     assert ctx.tuning == before
