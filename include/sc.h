@@ -150,6 +150,8 @@ typedef struct {
     uint64_t launches, events, graph_replays, graph_captures;
     uint64_t server_batches, server_events, server_rejected_again;
     double last_kernel_ms;   /* device time of the last fused/cluster launch (HIP events) */
+    double kernel_ms_total;  /* sum of those device times over the timed launches */
+    uint64_t kernels_timed;  /* number of launches summed in kernel_ms_total */
 } sc_stats;
 
 void sc_default_options(sc_options *opt);

@@ -78,7 +78,8 @@ class ScStats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("events", ctypes.c_uint64),
                 ("graph_replays", ctypes.c_uint64), ("graph_captures", ctypes.c_uint64),
                 ("server_batches", ctypes.c_uint64), ("server_events", ctypes.c_uint64),
-                ("server_rejected_again", ctypes.c_uint64), ("last_kernel_ms", ctypes.c_double)]
+                ("server_rejected_again", ctypes.c_uint64), ("last_kernel_ms", ctypes.c_double),
+                ("kernel_ms_total", ctypes.c_double), ("kernels_timed", ctypes.c_uint64)]
 
 
 _lib = None

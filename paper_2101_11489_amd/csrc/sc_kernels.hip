@@ -23,6 +23,7 @@
 //    (gain-corrected here) one lane per digi.
 // No MFMA: nothing here is a dense contraction.
 
+#include <atomic>
 #include <type_traits>
 
 #include "sc_internal.h"
@@ -1114,12 +1115,17 @@ __global__ void derive_calib_kernel(const float* noise, const float* gain, const
     out[i] = usable ? n : __builtin_inff();
 }
 
+// Resident tiles per CU of a kernel (its LDS and registers), queried once per shape.
 template <int W, int DW>
 int blocks_per_cu_for(bool dense) {
-    int nb = 0;
+    static std::atomic<int> known[2] = {0, 0};
+    int nb = known[dense].load(std::memory_order_relaxed);
+    if (nb > 0) return nb;
     hipError_t e = dense ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cluster_dense_kernel<W, DW>, kWave * W, 0)
                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_kernel<W, DW>, kWave * W, 0);
-    return e == hipSuccess ? nb : 1;
+    if (e != hipSuccess || nb < 1) return 1;
+    known[dense].store(nb, std::memory_order_relaxed);
+    return nb;
 }
 
 // Tile shapes: W waves per tile and chunk_digis digis per tile (chunk_digis / W per wave).

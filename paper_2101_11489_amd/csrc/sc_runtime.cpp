@@ -80,6 +80,7 @@ struct PinBuf {
 struct Workspace {
     DevBuf desc, res, state, queue, zs, fo, cl, adc, chst, dense;
     PinBuf h_desc, h_res, h_zs, h_fo;
+    std::vector<EventDesc> desc_on_device;   // what `desc` holds, so that equal uploads are skipped
     uint64_t generation = 0;   // bumps whenever a buffer that graphs capture moves
     hipError_t ensure_batch(uint32_t n_ev, uint32_t n_fed) {
         void* old[4] = {desc.p, res.p, state.p, queue.p};
@@ -91,6 +92,7 @@ struct Workspace {
         if ((e = queue.ensure(64)) != hipSuccess) return e;
         if ((e = h_desc.ensure(sizeof(EventDesc) * n_ev)) != hipSuccess) return e;
         if ((e = h_res.ensure(sizeof(EventResult) * n_ev)) != hipSuccess) return e;
+        if (old[0] != desc.p) desc_on_device.clear();
         if (old[0] != desc.p || old[1] != res.p || old[2] != state.p || old[3] != queue.p ||
             oldh[0] != h_desc.p || oldh[1] != h_res.p)
             ++generation;
@@ -186,6 +188,8 @@ void record_kernel_ms(sc_ctx* c) {
     float ms = 0;
     if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) {
         c->stats.last_kernel_ms = ms;
+        c->stats.kernel_ms_total += ms;
+        c->stats.kernels_timed++;
     } else {
         (void)hipGetLastError();
         c->stats.last_kernel_ms = -1.0;
@@ -330,11 +334,19 @@ FusedArgs fused_args(sc_ctx* c, Workspace& ws, uint32_t n) {
     return a;
 }
 
-// The device part of a batched launch: descriptors H2D, reset, fused kernel, results D2H.
-hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bool timed) {
+// The device part of a batched launch: descriptors H2D (unless the device already holds the
+// same ones; always when capturing a graph), reset, fused kernel, results D2H.
+hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bool timed,
+                         bool capturing = false) {
     hipError_t e;
-    if ((e = hipMemcpyAsync(ws.desc.p, ws.h_desc.p, sizeof(EventDesc) * n, hipMemcpyHostToDevice, s)))
-        return e;
+    const EventDesc* hd = ws.h_desc.as<EventDesc>();
+    const bool same = !capturing && ws.desc_on_device.size() == n &&
+                      std::memcmp(ws.desc_on_device.data(), hd, sizeof(EventDesc) * n) == 0;
+    if (!same) {
+        if ((e = hipMemcpyAsync(ws.desc.p, hd, sizeof(EventDesc) * n, hipMemcpyHostToDevice, s)))
+            return e;
+        ws.desc_on_device.assign(hd, hd + n);
+    }
     const FusedArgs a = fused_args(c, ws, n);
     if ((e = launch_reset(a, n * c->n_fed, s))) return e;
     if (timed && (e = hipEventRecord(c->ev0, s))) return e;
@@ -356,7 +368,7 @@ hipError_t enqueue_batch_graph(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t
         if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking))) return e;
         hipGraph_t g;
         if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal))) return e;
-        e = enqueue_batch(c, ws, n, cs, true);
+        e = enqueue_batch(c, ws, n, cs, true, true);
         hipError_t e2 = hipStreamEndCapture(cs, &g);
         (void)hipStreamDestroy(cs);
         if (e) return e;
@@ -369,6 +381,8 @@ hipError_t enqueue_batch_graph(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t
         c->stats.graph_captures++;
     }
     c->stats.graph_replays++;
+    const EventDesc* hd = ws.h_desc.as<EventDesc>();
+    ws.desc_on_device.assign(hd, hd + n);   // the replay uploads the current descriptors
     return hipGraphLaunch(it->second, s);
 }
 
@@ -878,6 +892,7 @@ sc_status sc_cluster(sc_ctx* c, const uint8_t* adc_dense, sc_mem in_mem, sc_clus
     Staged st;
     s0 = stage_batch(c, ws, &dummy, 1, &o, c->stream, st);
     if (s0 != SC_OK) return s0;
+    ws.desc_on_device.clear();
     SC_HIP(c, hipMemcpyAsync(ws.desc.p, ws.h_desc.p, sizeof(EventDesc), hipMemcpyHostToDevice, c->stream));
     FusedArgs a = fused_args(c, ws, 1);
     SC_HIP(c, launch_reset(a, c->n_fed, c->stream));

@@ -62,6 +62,34 @@ def test_event_alone_equals_event_in_any_batch(full):
     compare_clusters(alone[0][0], alone[0][1], refs[3], "alone")
 
 
+def test_repeated_and_alternating_batches(full):
+    # the same prepared batch again (descriptors already on the device), two batches of the same
+    # size in turn, and a dense sc_cluster call in between (which reuses the descriptor buffer)
+    cal, evs, refs, ctx = full
+    devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs]
+    outs_a = [ctx.output(*sc.safe_caps(d)) for d in devs[:4]]
+    outs_b = [ctx.output(*sc.safe_caps(d)) for d in devs[4:]]
+    a, b = ctx.batch(devs[:4], outs_a), ctx.batch(devs[4:], outs_b)
+    for g in (0, 1):
+        ctx.tuning = {"use_graph": g}
+        for rep, (bt, outs, rr) in enumerate([(a, outs_a, refs[:4]), (a, outs_a, refs[:4]),
+                                              (b, outs_b, refs[4:]), (a, outs_a, refs[:4]),
+                                              (b, outs_b, refs[4:]), (b, outs_b, refs[4:])]):
+            for o in outs:
+                o.cl.zero_()
+                o.adc.zero_()
+            rc, _ = ctx.process_batch(bt)
+            assert rc == sc.SC_OK
+            for o, ref in zip(outs, rr):
+                compare_clusters(*o.to_numpy()[:2], ref, f"graph {g} call {rep}")
+            if rep == 3:
+                dense, _ = ctx.unpack(devs[0])
+                out = ctx.output(*sc.safe_caps(devs[0]))
+                ctx.cluster(dense, out)
+                compare_clusters(*out.to_numpy()[:2], refs[0], "dense in between")
+    ctx.tuning = {"use_graph": 1}
+
+
 def test_graph_replays_match_eager(full):
     cal, evs, refs, ctx = full
     devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs[:4]]
