@@ -263,23 +263,24 @@ __device__ WalkResult stage_and_walk(TileSmem<W, DW>& sm, const uint8_t* g, uint
         const uint32_t delta = stage_bytes<kWave * W>(sm, threadIdx.x, g, L, gains);
         tile_sync();
         if (wave_index<W>() == 0u) {
-            // lane k (mod 64) keeps channel k's record position and length. Branch-free steps:
-            // after the first record that does not fit the FED, pos stays put and the remaining
-            // steps only re-read (inside the stage) without effect.
+            // lane k (mod 64) keeps channel k's record position and length. Branch-free steps
+            // whose serial chain is only read, add, clamp: a record fits the FED when the next
+            // position is <= L, and since positions only grow, the records that fit come first
+            // (past the first one that does not, the reads stay inside the stage and are unused).
             constexpr uint32_t omax = TileSmem<W, DW>::kStageBytes - 2;
-            uint32_t pos = 0, bad_from = kNch;
+            uint32_t pos = 0, good = 0;
             uint32_t vpos0 = 0, vpos1 = 0, vlen0 = 0, vlen1 = 0;
             auto step = [&](uint32_t k, uint32_t& vpos, uint32_t& vlen) {
                 uint32_t o = pos + delta;
                 o = o < omax ? o : omax;
                 const uint32_t P =
-                    uni((uint32_t)sm.stage[o] | ((uint32_t)sm.stage[o + 1] << 8));
-                const bool ok = bad_from == (uint32_t)kNch && pos + 2 <= L && pos + 2 + P <= L;
-                bad_from = (bad_from == (uint32_t)kNch && !ok) ? k : bad_from;
+                    uni((uint32_t)sm.stage[o] | ((uint32_t)sm.stage[o + 1] << 8)) & 0xffffu;
+                const uint32_t nxt = pos + 2u + P;
+                good += nxt <= L ? 1u : 0u;
                 const bool mine = lane() == (k & 63u);
                 vpos = mine ? pos + 2 : vpos;
                 vlen = mine ? P : vlen;
-                pos = ok ? pos + 2 + P : pos;
+                pos = nxt;
             };
 #pragma unroll 8
             for (uint32_t k = 0; k < 64u; ++k) step(k, vpos0, vlen0);
@@ -289,8 +290,8 @@ __device__ WalkResult stage_and_walk(TileSmem<W, DW>& sm, const uint8_t* g, uint
             sm.ch_len[lane()] = (uint16_t)vlen0;
             sm.ch_pos[64 + lane()] = vpos1;   // entries 96..127 are never read
             sm.ch_len[64 + lane()] = (uint16_t)vlen1;
-            sm.walk[0] = bad_from;
-            sm.walk[1] = (bad_from == (uint32_t)kNch && pos < L) ? 1u : 0u;
+            sm.walk[0] = good;
+            sm.walk[1] = (good == (uint32_t)kNch && pos < L) ? 1u : 0u;
             sm.walk[2] = delta;
         }
     } else {
@@ -827,26 +828,20 @@ __device__ __forceinline__ void emit_status(TileSmem<W, DW>& sm, uint32_t c_lo, 
 template <int W, int DW, class BuildFn>
 __device__ void cluster_group(const FusedArgs& A, TileSmem<W, DW>& sm, const EventDesc& ev,
                               uint32_t e, uint32_t f, uint32_t w, uint32_t n_chunks,
-                              uint32_t total, BuildFn build) {
+                              BuildFn build) {
     const uint32_t n_fed = A.cal.n_fed;
     unsigned long long* row = A.tile_state + (size_t)e * n_fed;
     uint32_t* dl = sm.digi + w * DW;
     const uint8_t* cf = sm.chunk_first[w];
-    uint32_t n_cl = 0, n_adc = 0;
-    // counts: one pass over the group (kept for the writes), or over each chunk
-    if (n_chunks == 1) {
-        build(uni(cf[0]), uni(cf[1]));
-        form_pass(dl, total, A.cal, f, n_cl, n_adc);
-    } else {
-        for (uint32_t ci = 0; ci < n_chunks; ++ci) {
-            const uint32_t c0 = uni(cf[ci]), c1 = uni(cf[ci + 1]);
-            build(c0, c1);
-            const uint32_t nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
-            uint32_t ccl, cadc;
-            form_pass(dl, nd, A.cal, f, ccl, cadc);
-            n_cl += ccl;
-            n_adc += cadc;
-        }
+    // counts: one pass over each chunk; the last chunk stays in the list for its writes
+    uint32_t n_cl = 0, n_adc = 0, last_cl = 0, last_adc = 0, last_nd = 0;
+    for (uint32_t ci = 0; ci < n_chunks; ++ci) {
+        const uint32_t c0 = uni(cf[ci]), c1 = uni(cf[ci + 1]);
+        build(c0, c1);
+        last_nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
+        form_pass(dl, last_nd, A.cal, f, last_cl, last_adc);
+        n_cl += last_cl;
+        n_adc += last_adc;
     }
     // the FED's counts and offsets
     uint32_t f_cl = n_cl, f_adc = n_adc, pre_cl = 0, pre_adc = 0;
@@ -878,21 +873,20 @@ __device__ void cluster_group(const FusedArgs& A, TileSmem<W, DW>& sm, const Eve
         ex_adc = uni(sm.grp_cnt[W][1]);
         err = uni(sm.grp_cnt[W][2]);
     }
-    // writes (the chunks again for a chunked group)
-    if (n_chunks == 1) {
-        write_pass(sm, dl, total, f, ev, ex_cl + pre_cl, ex_adc + pre_adc);
-    } else {
-        uint32_t bc = ex_cl + pre_cl, ba = ex_adc + pre_adc;
-        for (uint32_t ci = 0; ci < n_chunks; ++ci) {
-            const uint32_t c0 = uni(cf[ci]), c1 = uni(cf[ci + 1]);
-            build(c0, c1);
-            const uint32_t nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
-            uint32_t ccl, cadc;
-            form_pass(dl, nd, A.cal, f, ccl, cadc);
-            write_pass(sm, dl, nd, f, ev, bc, ba);
-            bc += ccl;
-            ba += cadc;
-        }
+    // writes: the last chunk first (still formed in the list), then the earlier chunks of a
+    // chunked group, built and formed again
+    const uint32_t bc = ex_cl + pre_cl, ba = ex_adc + pre_adc;
+    write_pass(sm, dl, last_nd, f, ev, bc + n_cl - last_cl, ba + n_adc - last_adc);
+    uint32_t oc = bc, oa = ba;
+    for (uint32_t ci = 0; ci + 1 < n_chunks; ++ci) {
+        const uint32_t c0 = uni(cf[ci]), c1 = uni(cf[ci + 1]);
+        build(c0, c1);
+        const uint32_t nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
+        uint32_t ccl, cadc;
+        form_pass(dl, nd, A.cal, f, ccl, cadc);
+        write_pass(sm, dl, nd, f, ev, oc, oa);
+        oc += ccl;
+        oa += cadc;
     }
     // uniform branches; every lane stores the same values
     if (w == 0u) {
@@ -950,7 +944,7 @@ __device__ void zs_tile(const FusedArgs& A, TileSmem<W, DW>& sm, uint32_t e, uin
         if (fits) build_zs(sm, w, dl, (const uint8_t*)(sm.stage + delta), c0, c1);
         else      build_zs(sm, w, dl, gc(g), c0, c1);
     };
-    cluster_group(A, sm, ev, e, f, w, n_chunks, total, build);
+    cluster_group(A, sm, ev, e, f, w, n_chunks, build);
 }
 
 // ---- one FED tile from dense ADC rows (single event) --------------------------------------
@@ -979,7 +973,7 @@ __device__ void dense_tile(const FusedArgs& A, TileSmem<W, DW>& sm, const uint8_
         [&](uint32_t ch) { return count_dense_row(rows + ch * kStripsPerChannel); }, total);
     uint32_t* dl = sm.digi + w * DW;
     auto build = [&](uint32_t c0, uint32_t c1) { build_dense(sm, w, dl, rows, c0, c1); };
-    cluster_group(A, sm, ev, 0, f, w, n_chunks, total, build);
+    cluster_group(A, sm, ev, 0, f, w, n_chunks, build);
 }
 
 // ---- kernels --------------------------------------------------------------------------------
