@@ -162,6 +162,15 @@ __device__ __forceinline__ uint32_t d_strip(uint32_t d) { return (d >> 8) & 255u
 __device__ __forceinline__ uint32_t d_ch(uint32_t d) { return (d >> 16) & 127u; }
 __device__ __forceinline__ uint32_t d_pos(uint32_t d) { return (d >> 8) & 0x7fffu; }
 
+// The little-endian u16 at byte o of an LDS buffer of NB bytes (4-byte aligned), from the two
+// aligned words around it: LDS reads at odd addresses stall. The caller keeps o + 1 < NB.
+template <uint32_t NB>
+__device__ __forceinline__ uint32_t lds_u16(const uint8_t* buf, uint32_t o) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(buf);
+    const uint32_t i = o >> 2, i1 = i + 1u < NB / 4u ? i + 1u : i;
+    return __builtin_amdgcn_alignbyte(w[i1], w[i], o & 3u) & 0xffffu;
+}
+
 template <int W, int DW>
 struct TileSmem {
     static constexpr int kStageBytes = 6656;   // a FED of full-detector events at 5 % occupancy
@@ -273,8 +282,7 @@ __device__ WalkResult stage_and_walk(TileSmem<W, DW>& sm, const uint8_t* g, uint
             auto step = [&](uint32_t k, uint32_t& vpos, uint32_t& vlen) {
                 uint32_t o = pos + delta;
                 o = o < omax ? o : omax;
-                const uint32_t P =
-                    uni((uint32_t)sm.stage[o] | ((uint32_t)sm.stage[o + 1] << 8)) & 0xffffu;
+                const uint32_t P = uni(lds_u16<TileSmem<W, DW>::kStageBytes>(sm.stage, o));
                 const uint32_t nxt = pos + 2u + P;
                 good += nxt <= L ? 1u : 0u;
                 const bool mine = lane() == (k & 63u);
@@ -672,7 +680,7 @@ __device__ __forceinline__ u32x4 make_record(uint32_t fed, uint32_t dw, uint32_t
     const uint32_t strip = d_strip(dw);
     const uint32_t first = strip - rp, width = rp + 1u;
     // barycenter: sum (s+1/2) c / sum c = (2M + C) / (2C), numerator and denominator exact
-    const float bary = C ? (float)((double)(2ull * M + C) / (2.0 * (double)C))
+    const float bary = C ? (float)((2.0 * (double)M + (double)C) / (2.0 * (double)C))
                          : (float)first + (float)width * 0.5f;
     return u32x4{fed * kNch + d_ch(dw), first | (width << 16), C, __float_as_uint(bary)};
 }
@@ -687,10 +695,15 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
     gmut<u32x4>* cl_out = gm(reinterpret_cast<u32x4*>(ev.cl));
     OpenCluster oc{0u, 0u, 0u, 0u, 0u, u32x4{0u, 0u, 0u, 0u}};
     uint32_t rc = base_cl, pa = base_adc;
+    // the digi word and the APV gain of the next step are read while this step runs
+    auto gain_of = [&](uint32_t d) { return sm.gain[2 * d_ch(d) + (d_strip(d) >> 7)]; };
+    uint32_t d_next = lane() < nd ? dl[lane()] : 0u;
+    float g_next = gain_of(d_next);
     for (uint32_t base = 0; base < nd; base += kWave) {
-        const uint32_t j = base + lane();
-        const bool valid = j < nd;
-        const uint32_t d = valid ? dl[j] : 0u;
+        const uint32_t d = d_next;
+        const float g = g_next;
+        const uint32_t jn = base + kWave + lane();
+        d_next = jn < nd ? dl[jn] : 0u;
         const bool act = (d & kActBit) != 0u;
         const bool cont = (d & kContBit) != 0u;
         const bool cont0 = (__ballot(cont) & 1ull) != 0ull;
@@ -709,8 +722,7 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         const bool member = act && run_acc;
         uint32_t c = 0;
         if (member) {
-            const float q = __builtin_rintf((float)d_adc(d) /
-                                            sm.gain[2 * d_ch(d) + (d_strip(d) >> 7)]);
+            const float q = __builtin_rintf((float)d_adc(d) / g);
             c = q > 65535.0f ? 65535u : (uint32_t)q;
         }
         const uint64_t mb = __ballot(member);
@@ -751,6 +763,7 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         oc.C = last_lane(C);
         oc.M = last_lane(M);
         oc.rec = u32x4{last_lane(rec.x), last_lane(rec.y), last_lane(rec.z), last_lane(rec.w)};
+        g_next = gain_of(d_next);
     }
     if (oc.open && rc < ev.cap_cl) cl_out[rc] = oc.rec;
     wave_sync();
