@@ -108,14 +108,21 @@ __device__ __forceinline__ void run_sums(A& a, B& b, uint32_t r) {
     run_sum_step<0x143, 0xc>(a, b, l >= 32u && r + 32u > l);
 }
 
+// Inclusive sum over the wavefront in six DPP steps: row_shr 1, 2, 4, 8 inside rows of 16 lanes,
+// then row_bcast:15 into rows 1 and 3 and row_bcast:31 into rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x += dpp_in<0x111, 0xf>(x);
+    x += dpp_in<0x112, 0xf>(x);
+    x += dpp_in<0x114, 0xf>(x);
+    x += dpp_in<0x118, 0xf>(x);
+    x += dpp_in<0x142, 0xa>(x);
+    x += dpp_in<0x143, 0xc>(x);
+    return x;
+}
+
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t& total) {
-    uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t y = __shfl_up(x, d, kWave);
-        if ((int)lane() >= d) x += y;
-    }
-    total = uni(__shfl(x, kWave - 1, kWave));
+    const uint32_t x = wave_incl_scan(v);
+    total = last_lane(x);
     return x - v;
 }
 
@@ -130,11 +137,7 @@ __device__ __forceinline__ uint32_t seg16_excl_scan(uint32_t v, uint32_t& total)
     return x - v;
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return uni(v);
-}
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return last_lane(wave_incl_scan(v)); }
 
 // Control-flow rule of these kernels: no branch on a lane-dependent, loop-invariant condition
 // (lane() == 0 and the like) around the persistent tile loop or the chunk loops. The middle end
@@ -1001,11 +1004,10 @@ __device__ __forceinline__ uint32_t next_tile(TileSmem<W, DW>& sm, uint32_t* que
     if constexpr (W == 1) {
         return uni(atomicAdd(queue, lane() == 0u ? 1u : 0u));
     } else {
+        // wave 0 rewrites walk[3] only after the barrier that ends the tile: one barrier here
         if (wave_index<W>() == 0u) sm.walk[3] = uni(atomicAdd(queue, lane() == 0u ? 1u : 0u));
         tile_sync();
-        const uint32_t t = uni(sm.walk[3]);
-        tile_sync();
-        return t;
+        return uni(sm.walk[3]);
     }
 }
 
