@@ -715,13 +715,12 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
             if (rc < ev.cap_cl) cl_out[rc] = oc.rec;   // same record from every lane
             rc += 1;
         }
-        // members: active digis whose run head is accepted
-        const bool head = act && !cont;
-        const uint64_t hb = __ballot(head);
-        const uint64_t ab = __ballot(head && (d & kAccBit));
-        const uint64_t hb_le = hb & mask_le();
-        const bool run_acc = hb_le ? ((ab >> (63u - (uint32_t)__clzll((long long)hb_le))) & 1ull)
-                                   : (oc.acc != 0u);
+        // members: active digis whose run head is accepted (the head of lane 0's run lies in an
+        // earlier step when lane 0 continues it)
+        uint32_t lhead;
+        const uint32_t lrp0 = local_run_pos(act, cont, lhead);
+        const uint64_t ab = __ballot(act && !cont && (d & kAccBit));
+        const bool run_acc = (lhead == 0u && cont0) ? (oc.acc != 0u) : ((ab >> lhead) & 1ull) != 0ull;
         const bool member = act && run_acc;
         uint32_t c = 0;
         if (member) {
@@ -735,8 +734,6 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         }
         pa += popc(mb);
         // run positions, charge and strip-weighted charge along member runs
-        uint32_t lhead;
-        const uint32_t lrp0 = local_run_pos(act, cont, lhead);
         const uint32_t rp = lrp0 + ((act && cont0 && lhead == 0u) ? oc.rp + 1u : 0u);
         const uint32_t lrp = member ? lrp0 : 0u;
         uint32_t C = c;
