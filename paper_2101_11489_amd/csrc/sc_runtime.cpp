@@ -81,6 +81,7 @@ struct Workspace {
     DevBuf desc, res, state, queue, zs, fo, cl, adc, chst, dense;
     PinBuf h_desc, h_res, h_zs, h_fo;
     std::vector<EventDesc> desc_on_device;   // what `desc` holds, so that equal uploads are skipped
+    bool clean = false;        // look-back words, queue and results zeroed (over their capacity)
     uint64_t generation = 0;   // bumps whenever a buffer that graphs capture moves
     hipError_t ensure_batch(uint32_t n_ev, uint32_t n_fed) {
         void* old[4] = {desc.p, res.p, state.p, queue.p};
@@ -93,6 +94,7 @@ struct Workspace {
         if ((e = h_desc.ensure(sizeof(EventDesc) * n_ev)) != hipSuccess) return e;
         if ((e = h_res.ensure(sizeof(EventResult) * n_ev)) != hipSuccess) return e;
         if (old[0] != desc.p) desc_on_device.clear();
+        if (old[1] != res.p || old[2] != state.p || old[3] != queue.p) clean = false;
         if (old[0] != desc.p || old[1] != res.p || old[2] != state.p || old[3] != queue.p ||
             oldh[0] != h_desc.p || oldh[1] != h_res.p)
             ++generation;
@@ -137,6 +139,7 @@ struct sc_ctx {
     std::string last_error;
     Workspace ws;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t done = nullptr;   // the results of a synchronous batch are on the host
     sc_stats stats{};
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::unique_ptr<Server> server;
@@ -334,6 +337,18 @@ FusedArgs fused_args(sc_ctx* c, Workspace& ws, uint32_t n) {
     return a;
 }
 
+// Zeroes the look-back words, the queue and the results over their whole capacity, for whatever
+// batch comes next; enqueued after a synchronous batch has handed its results over, so that it
+// runs while the host takes them.
+hipError_t enqueue_clean(sc_ctx* c, Workspace& ws, hipStream_t s) {
+    const uint32_t n_res = (uint32_t)(ws.res.n / sizeof(EventResult));
+    const uint32_t n_state = (uint32_t)(ws.state.n / sizeof(unsigned long long));
+    FusedArgs a = fused_args(c, ws, n_res);
+    hipError_t e = launch_reset(a, n_state, s);
+    if (e == hipSuccess) ws.clean = true;
+    return e;
+}
+
 // The device part of a batched launch: descriptors H2D (unless the device already holds the
 // same ones; always when capturing a graph), reset, fused kernel, results D2H.
 hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bool timed,
@@ -348,10 +363,13 @@ hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bo
         ws.desc_on_device.assign(hd, hd + n);
     }
     const FusedArgs a = fused_args(c, ws, n);
-    if ((e = launch_reset(a, n * c->n_fed, s))) return e;
+    if (capturing || !ws.clean) {
+        if ((e = launch_reset(a, n * c->n_fed, s))) return e;
+    }
     if (timed && (e = hipEventRecord(c->ev0, s))) return e;
     const uint32_t grid = grid_for(c, n * c->n_fed, false);
     if ((e = launch_fused(a, c->tuning.tile_waves, c->tuning.chunk_digis, grid, s))) return e;
+    ws.clean = false;
     if (timed && (e = hipEventRecord(c->ev1, s))) return e;
     return hipMemcpyAsync(ws.h_res.p, ws.res.p, sizeof(EventResult) * n, hipMemcpyDeviceToHost, s);
 }
@@ -383,6 +401,7 @@ hipError_t enqueue_batch_graph(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t
     c->stats.graph_replays++;
     const EventDesc* hd = ws.h_desc.as<EventDesc>();
     ws.desc_on_device.assign(hd, hd + n);   // the replay uploads the current descriptors
+    ws.clean = false;
     return hipGraphLaunch(it->second, s);
 }
 
@@ -426,7 +445,9 @@ sc_status run_batch(sc_ctx* c, const sc_event* ev, uint32_t n, sc_clusters* out,
     const bool graph = allow_graph && c->tuning.use_graph;
     if (graph) SC_HIP(c, enqueue_batch_graph(c, c->ws, n, c->stream));
     else       SC_HIP(c, enqueue_batch(c, c->ws, n, c->stream, true));
-    SC_HIP(c, hipStreamSynchronize(c->stream));
+    SC_HIP(c, hipEventRecord(c->done, c->stream));
+    SC_HIP(c, enqueue_clean(c, c->ws, c->stream));
+    SC_HIP(c, hipEventSynchronize(c->done));
     record_kernel_ms(c);
     c->stats.launches++;
     c->stats.events += n;
@@ -772,7 +793,8 @@ sc_status sc_create(const sc_calib* cal, const sc_options* opt_in, sc_ctx** out)
             return fail(nullptr, SC_ERR_DEVICE, "hipStreamCreate");
         c->own_stream = true;
     }
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreateWithFlags(&c->done, hipEventDisableTiming) != hipSuccess)
         return fail(nullptr, SC_ERR_DEVICE, "hipEventCreate");
     const size_t n_strips = (size_t)cal->n_fed * kChannelsPerFed * kStripsPerChannel;
     const size_t n_apv = n_strips / kStripsPerApv;
@@ -811,6 +833,7 @@ void sc_destroy(sc_ctx* c) {
     if (c->d_gain) (void)hipFree(c->d_gain);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->done) (void)hipEventDestroy(c->done);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -855,6 +878,7 @@ sc_status sc_unpack(sc_ctx* c, const sc_event* ev, uint8_t* adc_dense, uint8_t* 
     SC_HIP(c, launch_reset(a, 0, c->stream));
     SC_HIP(c, hipEventRecord(c->ev0, c->stream));
     SC_HIP(c, launch_unpack(zs, fo, c->n_fed, d_dense, d_st, a.res, c->stream));
+    ws.clean = false;
     SC_HIP(c, hipEventRecord(c->ev1, c->stream));
     SC_HIP(c, hipMemcpyAsync(ws.h_res.p, ws.res.p, sizeof(EventResult), hipMemcpyDeviceToHost, c->stream));
     if (out_mem == SC_MEM_HOST) {
@@ -896,6 +920,7 @@ sc_status sc_cluster(sc_ctx* c, const uint8_t* adc_dense, sc_mem in_mem, sc_clus
     SC_HIP(c, hipMemcpyAsync(ws.desc.p, ws.h_desc.p, sizeof(EventDesc), hipMemcpyHostToDevice, c->stream));
     FusedArgs a = fused_args(c, ws, 1);
     SC_HIP(c, launch_reset(a, c->n_fed, c->stream));
+    ws.clean = false;
     SC_HIP(c, hipEventRecord(c->ev0, c->stream));
     SC_HIP(c, launch_cluster_dense(d_in, a, c->tuning.tile_waves, c->tuning.chunk_digis,
                                    grid_for(c, c->n_fed, true), c->stream));
