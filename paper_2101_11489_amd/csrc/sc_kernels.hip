@@ -46,6 +46,7 @@ template <class T> __device__ __forceinline__ gconst<T>* gc(const T* p) { return
 template <class T> __device__ __forceinline__ gmut<T>* gm(T* p) { return (gmut<T>*)p; }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // 16-byte global accesses
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));   // two digi words
 
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 __device__ __forceinline__ uint64_t mask_lt() { return (1ull << lane()) - 1ull; }
@@ -562,92 +563,136 @@ __device__ __forceinline__ uint32_t local_run_pos(bool act, bool cont, uint32_t&
     return act ? lane() - lhead : 0u;
 }
 
-// One step of 64 digis [base, base+64) of the list dl: flags, runs, cluster threshold. Every
-// lane takes part (no divergent cross-lane work). Adds the flag bits to the digi words, marks
-// accepted run heads and counts clusters / member ADCs.
-__device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t nd, uint32_t d,
-                                          float n, const DeviceCalib& cal, OpenRun& open,
-                                          uint32_t& n_cl, uint32_t& my_adc, uint32_t& pending) {
-    const uint32_t j = base + lane();
-    const bool valid = j < nd;
-    const uint32_t a = d_adc(d), strip = d_strip(d), pos = d_pos(d);
-    const float af = (float)a;
-    const bool act = valid && af > cal.t_channel * n;
-    const bool sd = act && af > cal.t_seed * n;
-    // continues the previous digi: both active, same channel, adjacent strips
-    const uint32_t key = act ? pos + 1u : kNoKey;
-    uint32_t pk = from_prev_lane(key);
-    pk = lane() == 0u ? open.key : pk;
-    const bool cont = act && strip != 0u && pk == pos;
-    const bool cont0 = (__ballot(cont) & 1ull) != 0ull;
+// One step of 128 digis [base, base+128) of the list dl, two per lane: lane l holds digis
+// A = base + 2l and B = A + 1. Flags, runs, cluster threshold; every lane takes part (no divergent
+// cross-lane work). Adds the flag bits to the digi words, marks accepted run heads and counts
+// clusters / member ADCs.
+__device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t nd, uint32_t dA,
+                                          uint32_t dB, float nA, float nB, const DeviceCalib& cal,
+                                          OpenRun& open, uint32_t& n_cl, uint32_t& my_adc,
+                                          uint32_t& pending) {
+    const uint32_t l = lane();
+    const uint32_t jA = base + 2u * l, jB = jA + 1u;
+    const bool vA = jA < nd, vB = jB < nd;
+    const uint32_t aA = d_adc(dA), aB = d_adc(dB);
+    const uint32_t pA = d_pos(dA), pB = d_pos(dB);
+    const float afA = (float)aA, afB = (float)aB;
+    const bool actA = vA && afA > cal.t_channel * nA;
+    const bool actB = vB && afB > cal.t_channel * nB;
+    const bool sdA = actA && afA > cal.t_seed * nA;
+    const bool sdB = actB && afB > cal.t_seed * nB;
+    // continues the previous digi: both active, same channel, adjacent strips (B follows A in
+    // the lane, A follows the previous lane's B)
+    const uint32_t keyA = actA ? pA + 1u : kNoKey;
+    const uint32_t keyB = actB ? pB + 1u : kNoKey;
+    const bool contB = actB && d_strip(dB) != 0u && keyA == pB;
+    uint32_t pk = from_prev_lane(keyB);
+    pk = l == 0u ? open.key : pk;
+    const bool contA = actA && d_strip(dA) != 0u && pk == pA;
+    const bool cont0 = (__ballot(contA) & 1ull) != 0ull;
     // the run open at the end of the previous step ends before this step
     if (open.key != kNoKey && !cont0 && open.mark) {
         dl[open.head] |= open.mark;   // same word, same value from every lane
         if (open.mark == kAccBit) {
             n_cl += 1;
-            my_adc += lane() == 0u ? open.rp + 1u : 0u;
+            my_adc += l == 0u ? open.rp + 1u : 0u;
         } else {
             pending += 1;
         }
     }
-    uint32_t lhead;
-    const uint32_t lrp = local_run_pos(act, cont, lhead);
-    const bool from_open = cont0 && lhead == 0u;   // my run began in an earlier step
-    const uint32_t rp = lrp + ((act && from_open) ? open.rp + 1u : 0u);
-    // sums along the run: noise squares (tree order), raw charge, seeds
-    float S = act ? n * n : 0.0f;
-    uint32_t Q = act ? a + (sd ? 0x10000u : 0u) : 0u;
+    // run positions: distance to the nearest run head at or below (digi A of lane 0 heads the
+    // part of its run that lies in the step)
+    const bool hA = actA && (!contA || l == 0u);
+    const bool hB = actB && !contB;
+    const uint64_t ha = __ballot(hA) & mask_le(), hb = __ballot(hB) & mask_lt();
+    const uint32_t qa = ha ? 2u * (63u - (uint32_t)__clzll((long long)ha)) + 1u : 0u;
+    const uint32_t qb = hb ? 2u * (63u - (uint32_t)__clzll((long long)hb)) + 2u : 0u;
+    const uint32_t headA = (qa > qb ? qa : qb) - 1u;   // position in the step (A: 2l, B: 2l+1)
+    const uint32_t lrpA = actA ? 2u * l - headA : 0u;
+    const uint32_t lrpB = contB ? lrpA + 1u : 0u;
+    const bool fromA = actA && cont0 && headA == 0u;   // A's run began in an earlier step
+    const uint32_t carry = open.rp + 1u;
+    const uint32_t rpA = lrpA + (fromA ? carry : 0u);
+    const uint32_t rpB = lrpB + ((contB && fromA) ? carry : 0u);
+    // sums along the runs: noise squares (tree order), raw charge, seeds. Each lane's share of
+    // the run of its digi B is summed across lanes; digi A takes the previous lane's total.
+    float SA = actA ? nA * nA : 0.0f, SB = actB ? nB * nB : 0.0f;
+    uint32_t QA = actA ? aA + (sdA ? 0x10000u : 0u) : 0u;
+    uint32_t QB = actB ? aB + (sdB ? 0x10000u : 0u) : 0u;
     if (cont0) {
-        const bool l0 = lane() == 0u;
-        S = l0 ? S + open.S : S;
-        Q = l0 ? Q + open.Q : Q;
+        const bool l0 = l == 0u;
+        SA = l0 ? SA + open.S : SA;
+        QA = l0 ? QA + open.Q : QA;
     }
-    run_sums(S, Q, lrp);
-    if (valid) dl[j] = d | (act ? kActBit : 0u) | (sd ? kSeedBit : 0u) | (cont ? kContBit : 0u);
-    // runs that end inside this step; lane 63's run may go on, so it stays open with its
-    // threshold decision as it stands
-    const bool next_cont = from_next_lane(cont ? 1u : 0u) != 0u;
-    const bool at_end = act && !next_cont;
-    const uint32_t mark = cluster_mark(at_end, rp, Q, S, cal.t_cluster);
-    const bool ends = mark != 0u && lane() != 63u;
-    if (ends) dl[j - rp] |= mark;
-    const bool acc = ends && mark == kAccBit;
-    if (acc) my_adc += rp + 1u;
-    n_cl += popc(__ballot(acc));
-    pending += popc(__ballot(ends && mark == kRedoBit));
-    open.key = last_lane(key);
-    open.rp = last_lane(rp);
-    open.head = base + 63u - open.rp;
-    open.S = __uint_as_float(last_lane(__float_as_uint(S)));
-    open.Q = last_lane(Q);
-    open.mark = last_lane(mark);
+    SB = contB ? SB + SA : SB;
+    QB = contB ? QB + QA : QB;
+    // lanes back to where the run of digi B starts (0 outside runs)
+    const bool startB = hB || (contB && hA);
+    const uint64_t sb = __ballot(startB) & mask_le();
+    const uint32_t rl = actB ? l - (sb ? 63u - (uint32_t)__clzll((long long)sb) : 0u) : 0u;
+    run_sums(SB, QB, rl);
+    {
+        const float Sp = __uint_as_float(from_prev_lane(__float_as_uint(SB)));
+        const uint32_t Qp = from_prev_lane(QB);
+        const bool in = contA && l != 0u;
+        SA = in ? SA + Sp : SA;
+        QA = in ? QA + Qp : QA;
+    }
+    if (vA) dl[jA] = dA | (actA ? kActBit : 0u) | (sdA ? kSeedBit : 0u) | (contA ? kContBit : 0u);
+    if (vB) dl[jB] = dB | (actB ? kActBit : 0u) | (sdB ? kSeedBit : 0u) | (contB ? kContBit : 0u);
+    // runs that end inside this step; the run at digi B of lane 63 may go on, so it stays open
+    // with its threshold decision as it stands
+    const bool next_contA = from_next_lane(contA ? 1u : 0u) != 0u;
+    const bool endA = actA && !contB;
+    const bool endB = actB && !next_contA;
+    const uint32_t markA = cluster_mark(endA, rpA, QA, SA, cal.t_cluster);
+    const uint32_t markB = cluster_mark(endB, rpB, QB, SB, cal.t_cluster);
+    const bool eB = markB != 0u && l != 63u;
+    if (markA) dl[jA - rpA] |= markA;
+    if (eB) dl[jB - rpB] |= markB;
+    const bool accA = markA == kAccBit, accB = eB && markB == kAccBit;
+    my_adc += (accA ? rpA + 1u : 0u) + (accB ? rpB + 1u : 0u);
+    n_cl += popc(__ballot(accA)) + popc(__ballot(accB));
+    pending += popc(__ballot(markA == kRedoBit)) + popc(__ballot(eB && markB == kRedoBit));
+    open.key = last_lane(keyB);
+    open.rp = last_lane(rpB);
+    open.head = base + 127u - open.rp;
+    open.S = __uint_as_float(last_lane(__float_as_uint(SB)));
+    open.Q = last_lane(QB);
+    open.mark = last_lane(markB);
 }
 
-// Forming over the digi list dl[0, nd): steps of 64 digis, the loads of kBatch steps in flight.
+// Forming over the digi list dl[0, nd): steps of 128 digis, the loads of kBatch steps in flight.
 __device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const DeviceCalib& cal,
                                           uint32_t fed, uint32_t& n_cl, uint32_t& n_adc) {
-    constexpr int kBatch = 8;
+    constexpr int kBatch = 4;
+    constexpr uint32_t kStep = 2 * kWave;
     gconst<float>* noise = gc(cal.noise) + fed * kStripsPerFed;
     OpenRun open{kNoKey, 0u, 0u, 0.0f, 0u, 0u};
     uint32_t ncl = 0, my_adc = 0, pending = 0;
-    for (uint32_t b = 0; b < nd; b += kBatch * kWave) {
-        uint32_t d[kBatch];
-        float n[kBatch];
+    for (uint32_t b = 0; b < nd; b += kBatch * kStep) {
+        uint32_t dA[kBatch], dB[kBatch];
+        float nA[kBatch], nB[kBatch];
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
-            const uint32_t j = b + (uint32_t)(k * kWave) + lane();
-            d[k] = j < nd ? dl[j] : 0u;
+            const uint32_t j = b + (uint32_t)k * kStep + 2u * lane();
+            u32x2 w = {0u, 0u};
+            if (j < nd) w = *reinterpret_cast<const u32x2*>(dl + j);   // dl + j + 1 is inside the list
+            dA[k] = w.x;
+            dB[k] = j + 1u < nd ? w.y : 0u;
         }
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
-            const uint32_t j = b + (uint32_t)(k * kWave) + lane();
-            n[k] = j < nd ? noise[d_pos(d[k])] : 0.0f;
+            const uint32_t j = b + (uint32_t)k * kStep + 2u * lane();
+            nA[k] = j < nd ? noise[d_pos(dA[k])] : 0.0f;
+            nB[k] = j + 1u < nd ? noise[d_pos(dB[k])] : 0.0f;
         }
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
-            const uint32_t base = b + (uint32_t)(k * kWave);
+            const uint32_t base = b + (uint32_t)k * kStep;
             if (base < nd)
-                form_step(dl, base, nd, d[k], n[k], cal, open, ncl, my_adc, pending);
+                form_step(dl, base, nd, dA[k], dB[k], nA[k], nB[k], cal, open, ncl, my_adc,
+                          pending);
         }
     }
     if (open.key != kNoKey && open.mark) {
