@@ -733,82 +733,134 @@ __device__ __forceinline__ u32x4 make_record(uint32_t fed, uint32_t dw, uint32_t
     return u32x4{fed * kNch + d_ch(dw), first | (width << 16), C, __float_as_uint(bary)};
 }
 
-// Records and member ADCs of the digi list dl[0, nd) at their final positions. The member ADCs
-// are gain-corrected here: c = min(rint(adc / gain), 65535) with the FP32 quotient.
+// Gain-corrected ADC of a member digi: min(rint(adc / gain), 65535) with the FP32 quotient.
+__device__ __forceinline__ uint32_t corrected_adc(uint32_t d, float g) {
+    const float q = __builtin_rintf((float)d_adc(d) / g);
+    return q > 65535.0f ? 65535u : (uint32_t)q;
+}
+
+// Records and member ADCs of the digi list dl[0, nd) at their final positions, 128 digis per
+// step, two per lane (A = base + 2l, B = A + 1) as in forming. The member ADCs are
+// gain-corrected here.
 template <int W, int DW>
 __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint32_t* dl,
                                            uint32_t nd, uint32_t fed, const EventDesc& ev,
                                            uint32_t base_cl, uint32_t base_adc) {
+    constexpr uint32_t kStep = 2 * kWave;
     gmut<uint16_t>* adc_out = gm(ev.adc);
     gmut<u32x4>* cl_out = gm(reinterpret_cast<u32x4*>(ev.cl));
     OpenCluster oc{0u, 0u, 0u, 0u, 0u, u32x4{0u, 0u, 0u, 0u}};
     uint32_t rc = base_cl, pa = base_adc;
-    // the digi word and the APV gain of the next step are read while this step runs
+    const uint32_t l = lane();
+    // the digi words and APV gains of the next step are read while this step runs
     auto gain_of = [&](uint32_t d) { return sm.gain[2 * d_ch(d) + (d_strip(d) >> 7)]; };
-    uint32_t d_next = lane() < nd ? dl[lane()] : 0u;
-    float g_next = gain_of(d_next);
-    for (uint32_t base = 0; base < nd; base += kWave) {
-        const uint32_t d = d_next;
-        const float g = g_next;
-        const uint32_t jn = base + kWave + lane();
-        d_next = jn < nd ? dl[jn] : 0u;
-        const bool act = (d & kActBit) != 0u;
-        const bool cont = (d & kContBit) != 0u;
-        const bool cont0 = (__ballot(cont) & 1ull) != 0ull;
+    auto load = [&](uint32_t j, uint32_t& dA, uint32_t& dB) {
+        u32x2 w = {0u, 0u};
+        if (j < nd) w = *reinterpret_cast<const u32x2*>(dl + j);   // dl + j + 1 is inside the list
+        dA = w.x;
+        dB = j + 1u < nd ? w.y : 0u;
+    };
+    uint32_t nA, nB;
+    load(2u * l, nA, nB);
+    float gnA = gain_of(nA), gnB = gain_of(nB);
+    for (uint32_t base = 0; base < nd; base += kStep) {
+        const uint32_t dA = nA, dB = nB;
+        const float gA = gnA, gB = gnB;
+        load(base + kStep + 2u * l, nA, nB);
+        const bool actA = (dA & kActBit) != 0u, actB = (dB & kActBit) != 0u;
+        const bool contA = (dA & kContBit) != 0u, contB = (dB & kContBit) != 0u;
+        const bool cont0 = (__ballot(contA) & 1ull) != 0ull;
         // the cluster open at the end of the previous step is complete unless lane 0 continues it
         if (oc.open && !cont0) {
             if (rc < ev.cap_cl) cl_out[rc] = oc.rec;   // same record from every lane
             rc += 1;
         }
-        // members: active digis whose run head is accepted (the head of lane 0's run lies in an
-        // earlier step when lane 0 continues it)
-        uint32_t lhead;
-        const uint32_t lrp0 = local_run_pos(act, cont, lhead);
-        const uint64_t ab = __ballot(act && !cont && (d & kAccBit));
-        const bool run_acc = (lhead == 0u && cont0) ? (oc.acc != 0u) : ((ab >> lhead) & 1ull) != 0ull;
-        const bool member = act && run_acc;
-        uint32_t c = 0;
-        if (member) {
-            const float q = __builtin_rintf((float)d_adc(d) / g);
-            c = q > 65535.0f ? 65535u : (uint32_t)q;
+        // run heads and positions (digi A of lane 0 heads the part of its run in the step)
+        const bool hA = actA && (!contA || l == 0u);
+        const bool hB = actB && !contB;
+        const uint64_t HA = __ballot(hA), HB = __ballot(hB);
+        const uint64_t ha = HA & mask_le(), hb = HB & mask_lt();
+        const uint32_t qa = ha ? 2u * (63u - (uint32_t)__clzll((long long)ha)) + 1u : 0u;
+        const uint32_t qb = hb ? 2u * (63u - (uint32_t)__clzll((long long)hb)) + 2u : 0u;
+        const uint32_t headA = (qa > qb ? qa : qb) - 1u;   // position in the step
+        const uint32_t lrpA = actA ? 2u * l - headA : 0u;
+        const uint32_t lrpB = contB ? lrpA + 1u : 0u;
+        const bool fromA = actA && cont0 && headA == 0u;   // A's run began in an earlier step
+        const uint32_t carry = oc.rp + 1u;
+        const uint32_t rpA = lrpA + (fromA ? carry : 0u);
+        const uint32_t rpB = lrpB + ((contB && fromA) ? carry : 0u);
+        // members: active digis whose run head carries the accepted bit
+        const uint64_t abA = __ballot(actA && !contA && (dA & kAccBit));
+        const uint64_t abB = __ballot(hB && (dB & kAccBit));
+        const uint32_t hl = headA >> 1;
+        const bool accA = fromA ? (oc.acc != 0u)
+                                : ((((headA & 1u) ? abB : abA) >> hl) & 1ull) != 0ull;
+        const bool memA = actA && accA;
+        const bool memB = actB && (contB ? accA : ((abB >> l) & 1ull) != 0ull);
+        uint32_t cA = 0, cB = 0;
+        if (memA) cA = corrected_adc(dA, gA);
+        if (memB) cB = corrected_adc(dB, gB);
+        const uint64_t mbA = __ballot(memA), mbB = __ballot(memB);
+        {
+            const uint32_t p = pa + popc(mbA & mask_lt()) + popc(mbB & mask_lt());
+            if (memA && p < ev.cap_adc) adc_out[p] = (uint16_t)cA;
+            const uint32_t q = p + (memA ? 1u : 0u);
+            if (memB && q < ev.cap_adc) adc_out[q] = (uint16_t)cB;
         }
-        const uint64_t mb = __ballot(member);
-        if (member) {
-            const uint32_t p = pa + popc(mb & mask_lt());
-            if (p < ev.cap_adc) adc_out[p] = (uint16_t)c;
-        }
-        pa += popc(mb);
-        // run positions, charge and strip-weighted charge along member runs
-        const uint32_t rp = lrp0 + ((act && cont0 && lhead == 0u) ? oc.rp + 1u : 0u);
-        const uint32_t lrp = member ? lrp0 : 0u;
-        uint32_t C = c;
-        uint32_t M = d_strip(d) * c;
+        pa += popc(mbA) + popc(mbB);
+        // charge and strip-weighted charge along member runs: each lane's share of the run of
+        // its digi B is summed across lanes; digi A takes the previous lane's total
+        uint32_t CA = cA, MA = d_strip(dA) * cA;
         if (cont0 && oc.open) {
-            const bool l0 = lane() == 0u;
-            C = l0 ? C + oc.C : C;
-            M = l0 ? M + oc.M : M;
+            const bool l0 = l == 0u;
+            CA = l0 ? CA + oc.C : CA;
+            MA = l0 ? MA + oc.M : MA;
         }
-        run_sums(C, M, lrp);
-        // records of the clusters ending in this step; lane 63's record as it stands is kept
-        // for the next step, which stores it if the cluster does not go on
-        const bool next_cont = from_next_lane(cont ? 1u : 0u) != 0u;
-        const bool at_end = member && !next_cont;
-        const bool ends = at_end && lane() != 63u;
-        const uint64_t eb = __ballot(ends);
-        u32x4 rec = {0u, 0u, 0u, 0u};
-        if (at_end) rec = make_record(fed, d, rp, C, M);
-        if (ends) {
-            const uint32_t p = rc + popc(eb & mask_lt());
-            if (p < ev.cap_cl) cl_out[p] = rec;
+        uint32_t CB = cB + (contB ? CA : 0u), MB = d_strip(dB) * cB + (contB ? MA : 0u);
+        const bool startB = hB || (contB && hA);
+        const uint64_t sb = __ballot(startB) & mask_le();
+        const uint32_t rl = memB ? l - (sb ? 63u - (uint32_t)__clzll((long long)sb) : 0u) : 0u;
+        run_sums(CB, MB, rl);
+        {
+            const uint32_t Cp = from_prev_lane(CB), Mp = from_prev_lane(MB);
+            const bool in = contA && l != 0u;
+            CA = in ? CA + Cp : CA;
+            MA = in ? MA + Mp : MA;
         }
-        rc += popc(eb);
-        oc.open = (uint32_t)(mb >> 63);
-        oc.acc = (uint32_t)((__ballot(run_acc) >> 63) & 1ull);
-        oc.rp = last_lane(rp);
-        oc.C = last_lane(C);
-        oc.M = last_lane(M);
-        oc.rec = u32x4{last_lane(rec.x), last_lane(rec.y), last_lane(rec.z), last_lane(rec.w)};
-        g_next = gain_of(d_next);
+        // records of the clusters ending in this step (A before B in a lane); the record of
+        // digi B of lane 63 as it stands is kept for the next step, which stores it if the
+        // cluster does not go on
+        const bool next_contA = from_next_lane(contA ? 1u : 0u) != 0u;
+        const bool endA = memA && !contB;
+        const bool endB = memB && !next_contA;
+        const bool eB = endB && l != 63u;
+        // one record per lane first (A's where A ends, else B's), B's too where both end
+        u32x4 rec1 = {0u, 0u, 0u, 0u}, recB = {0u, 0u, 0u, 0u};
+        if (endA || endB) {
+            rec1 = make_record(fed, endA ? dA : dB, endA ? rpA : rpB, endA ? CA : CB,
+                               endA ? MA : MB);
+        }
+        const bool both = endA && endB;
+        if (__ballot(both) != 0ull) {
+            if (both) recB = make_record(fed, dB, rpB, CB, MB);
+        }
+        if (!endA) recB = rec1;
+        const uint64_t ebA = __ballot(endA), ebB = __ballot(eB);
+        {
+            const uint32_t p = rc + popc(ebA & mask_lt()) + popc(ebB & mask_lt());
+            if (endA && p < ev.cap_cl) cl_out[p] = rec1;
+            const uint32_t q = p + (endA ? 1u : 0u);
+            if (eB && q < ev.cap_cl) cl_out[q] = recB;
+        }
+        rc += popc(ebA) + popc(ebB);
+        oc.open = (uint32_t)(mbB >> 63);
+        oc.acc = (uint32_t)((__ballot(memB) >> 63) & 1ull);
+        oc.rp = last_lane(rpB);
+        oc.C = last_lane(CB);
+        oc.M = last_lane(MB);
+        oc.rec = u32x4{last_lane(recB.x), last_lane(recB.y), last_lane(recB.z), last_lane(recB.w)};
+        gnA = gain_of(nA);
+        gnB = gain_of(nB);
     }
     if (oc.open && rc < ev.cap_cl) cl_out[rc] = oc.rec;
     wave_sync();
