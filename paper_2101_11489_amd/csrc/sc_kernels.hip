@@ -12,15 +12,16 @@
 //    0 walks the 96 length fields in LDS (the channel map the paper builds on the CPU); then each
 //    wave takes a group of 96/W channels on its own: one lane per channel validates and expands
 //    the records into the wave's digi list in LDS;
-//  * cluster forming runs digi-parallel, 64 digis per step, with the calibration gathers of
-//    several steps in flight: the active/seed tests use one FP32 effective noise per strip
-//    (+inf for unusable strips, which never passes ADC > T*noise); a run is a chain of active
-//    digis on adjacent strips, and the sequential noise sum of each run is carried from lane to
-//    lane with DPP lane shifts, one strip position per iteration, so no lane walks memory;
+//  * cluster forming runs digi-parallel, 128 digis per step (two per lane), with the calibration
+//    gathers of several steps in flight: the active/seed tests use one FP32 effective noise per
+//    strip (+inf for unusable strips, which never passes ADC > T*noise); a run is a chain of
+//    active digis on adjacent strips, and its sums (noise squares, charge, seeds) come from a
+//    segmented DPP scan over the lanes; the noise-square sum, in tree order, only steers the
+//    cluster threshold, whose few undecidable runs are settled with the sequential sum;
 //  * the waves exchange their groups' counts in LDS; the tile publishes the FED's counts and looks
 //    back over the earlier FEDs of its event, 64 per load (decoupled look-back), for its output
 //    offsets; records are written by the lane of each cluster's last strip, member ADCs
-//    (gain-corrected here) one lane per digi.
+//    (gain-corrected here) one lane per digi, again 128 digis per step.
 // No MFMA: nothing here is a dense contraction.
 
 #include <atomic>
@@ -495,7 +496,7 @@ __device__ __forceinline__ uint32_t count_dense_row(const uint8_t* row) {
 }
 
 // ---- cluster forming, digi-parallel -------------------------------------------------------
-// Uniform state of the run still open at lane 63 of the previous step.
+// Uniform state of the run still open at the last digi of the previous step.
 struct OpenRun {
     uint32_t key;   // position + 1 of its last digi (kNoKey: no open run)
     uint32_t head;  // digi index of its first digi
@@ -554,13 +555,34 @@ __device__ void settle_runs(uint32_t* dl, uint32_t nd, gconst<float>* noise, flo
     }
 }
 
-// Local run position of each lane's digi in a step: distance to the nearest run head at or below
-// (lane 0 heads the part of its run that lies in the step). lhead: that head's lane.
-__device__ __forceinline__ uint32_t local_run_pos(bool act, bool cont, uint32_t& lhead) {
-    const uint64_t lh = __ballot(act && (!cont || lane() == 0u));
-    const uint64_t upto = lh & mask_le();
-    lhead = upto ? 63u - (uint32_t)__clzll((long long)upto) : 0u;
-    return act ? lane() - lhead : 0u;
+// Runs of a step of 128 digis, two per lane: digi A of lane l sits at position 2l, B at 2l + 1.
+// Digi A of lane 0 heads the part of its run that lies in the step. Run positions count from the
+// run's first digi, across steps too (carry: run position + 1 of the previous step's last digi).
+struct PairRuns {
+    uint32_t rpA, rpB;   // run positions of A and B
+    bool fromA;          // A's run began in an earlier step
+    uint32_t lanes;      // lanes back to where the run of B starts (0 when B is inactive)
+};
+__device__ __forceinline__ PairRuns pair_runs(bool actA, bool contA, bool actB, bool contB,
+                                              bool cont0, uint32_t carry) {
+    const uint32_t l = lane();
+    const bool hA = actA && (!contA || l == 0u);
+    const bool hB = actB && !contB;
+    // nearest head at or below A: heads A of lanes <= l (position 2j), heads B of lanes < l (2j+1)
+    const uint64_t ha = __ballot(hA) & mask_le(), hb = __ballot(hB) & mask_lt();
+    const uint32_t qa = ha ? 2u * (63u - (uint32_t)__clzll((long long)ha)) + 1u : 0u;
+    const uint32_t qb = hb ? 2u * (63u - (uint32_t)__clzll((long long)hb)) + 2u : 0u;
+    const uint32_t headA = (qa > qb ? qa : qb) - 1u;
+    const uint32_t lrpA = actA ? 2u * l - headA : 0u;
+    const uint32_t lrpB = contB ? lrpA + 1u : 0u;
+    PairRuns r;
+    r.fromA = actA && cont0 && headA == 0u;
+    r.rpA = lrpA + (r.fromA ? carry : 0u);
+    r.rpB = lrpB + ((contB && r.fromA) ? carry : 0u);
+    // the run of B starts in lane l when B heads it or continues an A that heads it
+    const uint64_t sb = __ballot(hB || (contB && hA)) & mask_le();
+    r.lanes = actB ? l - (sb ? 63u - (uint32_t)__clzll((long long)sb) : 0u) : 0u;
+    return r;
 }
 
 // One step of 128 digis [base, base+128) of the list dl, two per lane: lane l holds digis
@@ -600,20 +622,8 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
             pending += 1;
         }
     }
-    // run positions: distance to the nearest run head at or below (digi A of lane 0 heads the
-    // part of its run that lies in the step)
-    const bool hA = actA && (!contA || l == 0u);
-    const bool hB = actB && !contB;
-    const uint64_t ha = __ballot(hA) & mask_le(), hb = __ballot(hB) & mask_lt();
-    const uint32_t qa = ha ? 2u * (63u - (uint32_t)__clzll((long long)ha)) + 1u : 0u;
-    const uint32_t qb = hb ? 2u * (63u - (uint32_t)__clzll((long long)hb)) + 2u : 0u;
-    const uint32_t headA = (qa > qb ? qa : qb) - 1u;   // position in the step (A: 2l, B: 2l+1)
-    const uint32_t lrpA = actA ? 2u * l - headA : 0u;
-    const uint32_t lrpB = contB ? lrpA + 1u : 0u;
-    const bool fromA = actA && cont0 && headA == 0u;   // A's run began in an earlier step
-    const uint32_t carry = open.rp + 1u;
-    const uint32_t rpA = lrpA + (fromA ? carry : 0u);
-    const uint32_t rpB = lrpB + ((contB && fromA) ? carry : 0u);
+    const PairRuns pr = pair_runs(actA, contA, actB, contB, cont0, open.rp + 1u);
+    const uint32_t rpA = pr.rpA, rpB = pr.rpB;
     // sums along the runs: noise squares (tree order), raw charge, seeds. Each lane's share of
     // the run of its digi B is summed across lanes; digi A takes the previous lane's total.
     float SA = actA ? nA * nA : 0.0f, SB = actB ? nB * nB : 0.0f;
@@ -626,11 +636,7 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
     }
     SB = contB ? SB + SA : SB;
     QB = contB ? QB + QA : QB;
-    // lanes back to where the run of digi B starts (0 outside runs)
-    const bool startB = hB || (contB && hA);
-    const uint64_t sb = __ballot(startB) & mask_le();
-    const uint32_t rl = actB ? l - (sb ? 63u - (uint32_t)__clzll((long long)sb) : 0u) : 0u;
-    run_sums(SB, QB, rl);
+    run_sums(SB, QB, pr.lanes);
     {
         const float Sp = __uint_as_float(from_prev_lane(__float_as_uint(SB)));
         const uint32_t Qp = from_prev_lane(QB);
@@ -714,11 +720,11 @@ __device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const Devic
 }
 
 // ---- outputs ------------------------------------------------------------------------------
-// Uniform state of the member run still open at lane 63 of the previous write step.
+// Uniform state of the member run still open at the last digi of the previous write step.
 struct OpenCluster {
-    uint32_t open;   // 1: lane 63 of the previous step was a member
-    uint32_t acc;    // acceptance of the run at lane 63 (for the continuing lanes)
-    uint32_t rp;     // run position of lane 63's digi
+    uint32_t open;   // 1: the last digi of the previous step was a member
+    uint32_t acc;    // acceptance of that digi's run (for the digis that continue it)
+    uint32_t rp;     // run position of that digi
     uint32_t C, M;   // sums of c and strip*c so far
     u32x4 rec;       // its record as it stands (valid if the cluster ends there)
 };
@@ -775,26 +781,15 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
             if (rc < ev.cap_cl) cl_out[rc] = oc.rec;   // same record from every lane
             rc += 1;
         }
-        // run heads and positions (digi A of lane 0 heads the part of its run in the step)
-        const bool hA = actA && (!contA || l == 0u);
-        const bool hB = actB && !contB;
-        const uint64_t HA = __ballot(hA), HB = __ballot(hB);
-        const uint64_t ha = HA & mask_le(), hb = HB & mask_lt();
-        const uint32_t qa = ha ? 2u * (63u - (uint32_t)__clzll((long long)ha)) + 1u : 0u;
-        const uint32_t qb = hb ? 2u * (63u - (uint32_t)__clzll((long long)hb)) + 2u : 0u;
-        const uint32_t headA = (qa > qb ? qa : qb) - 1u;   // position in the step
-        const uint32_t lrpA = actA ? 2u * l - headA : 0u;
-        const uint32_t lrpB = contB ? lrpA + 1u : 0u;
-        const bool fromA = actA && cont0 && headA == 0u;   // A's run began in an earlier step
-        const uint32_t carry = oc.rp + 1u;
-        const uint32_t rpA = lrpA + (fromA ? carry : 0u);
-        const uint32_t rpB = lrpB + ((contB && fromA) ? carry : 0u);
-        // members: active digis whose run head carries the accepted bit
+        const PairRuns pr = pair_runs(actA, contA, actB, contB, cont0, oc.rp + 1u);
+        const uint32_t rpA = pr.rpA, rpB = pr.rpB;
+        // members: active digis whose run head carries the accepted bit; the head of A's run
+        // sits rpA positions back (in an earlier step when fromA)
         const uint64_t abA = __ballot(actA && !contA && (dA & kAccBit));
-        const uint64_t abB = __ballot(hB && (dB & kAccBit));
-        const uint32_t hl = headA >> 1;
-        const bool accA = fromA ? (oc.acc != 0u)
-                                : ((((headA & 1u) ? abB : abA) >> hl) & 1ull) != 0ull;
+        const uint64_t abB = __ballot(actB && !contB && (dB & kAccBit));
+        const uint32_t headA = 2u * l - (actA ? rpA : 0u);
+        const bool accA = pr.fromA ? (oc.acc != 0u)
+                                   : ((((headA & 1u) ? abB : abA) >> (headA >> 1)) & 1ull) != 0ull;
         const bool memA = actA && accA;
         const bool memB = actB && (contB ? accA : ((abB >> l) & 1ull) != 0ull);
         uint32_t cA = 0, cB = 0;
@@ -817,10 +812,7 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
             MA = l0 ? MA + oc.M : MA;
         }
         uint32_t CB = cB + (contB ? CA : 0u), MB = d_strip(dB) * cB + (contB ? MA : 0u);
-        const bool startB = hB || (contB && hA);
-        const uint64_t sb = __ballot(startB) & mask_le();
-        const uint32_t rl = memB ? l - (sb ? 63u - (uint32_t)__clzll((long long)sb) : 0u) : 0u;
-        run_sums(CB, MB, rl);
+        run_sums(CB, MB, pr.lanes);
         {
             const uint32_t Cp = from_prev_lane(CB), Mp = from_prev_lane(MB);
             const bool in = contA && l != 0u;
