@@ -362,9 +362,12 @@ __device__ __forceinline__ uint32_t check_channel(TileSmem<W, DW>& sm, P src, ui
         bool ok = true;
         while (q < len) {
             if (q + 2 > len) { ok = false; break; }
+            // both header bytes are read before any test, and the tests are combined without
+            // short-circuit branches, so a record costs one LDS round trip
             const uint32_t first = src[p + q], cnt = src[p + q + 1];
-            if (cnt == 0 || first + cnt > (uint32_t)kStripsPerChannel || first < next_free ||
-                q + 2 + cnt > len) { ok = false; break; }
+            const bool bad = (cnt == 0u) | (first + cnt > (uint32_t)kStripsPerChannel) |
+                             (first < next_free) | (q + 2 + cnt > len);
+            if (bad) { ok = false; break; }
             nd += cnt;
             next_free = first + cnt;
             q += 2 + cnt;
