@@ -167,20 +167,19 @@ __device__ __forceinline__ uint32_t d_strip(uint32_t d) { return (d >> 8) & 255u
 __device__ __forceinline__ uint32_t d_ch(uint32_t d) { return (d >> 16) & 127u; }
 __device__ __forceinline__ uint32_t d_pos(uint32_t d) { return (d >> 8) & 0x7fffu; }
 
-// The little-endian u16 at byte o of an LDS buffer of NB bytes (4-byte aligned), from the two
-// aligned words around it: LDS reads at odd addresses stall. The caller keeps o + 1 < NB.
-template <uint32_t NB>
+// The little-endian u16 at byte o of a 4-byte aligned LDS buffer, from the two aligned words
+// around it (one ds_read2): LDS reads at odd addresses stall. The caller keeps o + 1 inside the
+// buffer, which has four readable bytes past its end.
 __device__ __forceinline__ uint32_t lds_u16(const uint8_t* buf, uint32_t o) {
-    const uint32_t* w = reinterpret_cast<const uint32_t*>(buf);
-    const uint32_t i = o >> 2, i1 = i + 1u < NB / 4u ? i + 1u : i;
-    return __builtin_amdgcn_alignbyte(w[i1], w[i], o & 3u) & 0xffffu;
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(buf) + (o >> 2);
+    return __builtin_amdgcn_alignbyte(w[1], w[0], o & 3u) & 0xffffu;
 }
 
 template <int W, int DW>
 struct TileSmem {
     static constexpr int kStageBytes = 6656;   // a FED of full-detector events at 5 % occupancy
     static constexpr int kStageData = kStageBytes - 16;   // FED bytes that fit (alignment slack)
-    alignas(16) uint8_t stage[kStageBytes];              // the FED's bytes
+    alignas(16) uint8_t stage[kStageBytes + 16];         // the FED's bytes (+ readable pad)
     uint32_t digi[W * DW];                               // wave w: [w*DW, (w+1)*DW)
     alignas(16) float gain[2 * kNch];                    // the FED's APV gains
     uint32_t ch_pos[2 * kWave];   // 96 used; 128 so that two full-wave stores fit
@@ -287,7 +286,7 @@ __device__ WalkResult stage_and_walk(TileSmem<W, DW>& sm, const uint8_t* g, uint
             auto step = [&](uint32_t k, uint32_t& vpos, uint32_t& vlen) {
                 uint32_t o = pos + delta;
                 o = o < omax ? o : omax;
-                const uint32_t P = uni(lds_u16<TileSmem<W, DW>::kStageBytes>(sm.stage, o));
+                const uint32_t P = uni(lds_u16(sm.stage, o));
                 const uint32_t nxt = pos + 2u + P;
                 good += nxt <= L ? 1u : 0u;
                 const bool mine = lane() == (k & 63u);
