@@ -10,8 +10,8 @@
 //    calibration is reused from cache) or event-major;
 //  * the FED's bytes and gains are staged into LDS with all 16-byte loads in flight at once; wave
 //    0 walks the 96 length fields in LDS (the channel map the paper builds on the CPU); then each
-//    wave takes a group of 96/W channels on its own: one lane per channel validates and expands
-//    the records into the wave's digi list in LDS;
+//    wave takes a group of 96/W channels on its own: one lane per channel validates the records
+//    and marks where each begins in the wave's digi list in LDS, and one lane per digi fills it;
 //  * cluster forming runs digi-parallel, 128 digis per step (two per lane), with the calibration
 //    gathers of several steps in flight: the active/seed tests use one FP32 effective noise per
 //    strip (+inf for unusable strips, which never passes ADC > T*noise); a run is a chain of
@@ -416,34 +416,78 @@ __device__ uint32_t plan_chunks(TileSmem<W, DW>& sm, uint32_t w, uint32_t c_lo, 
     return n_chunks;
 }
 
-// Expand the records of channels [c0, c1) into the digi list dl (one lane per channel); the ADC
-// bytes of a run are read four at a time.
-template <class P, int W, int DW>
+// Expand the records of channels [c0, c1) into the digi list dl.
+// From the staged FED (LDS) in two passes: one lane per channel writes, at the first digi slot
+// of each of its records, a marker (bit 31 | source offset of the ADC bytes << 15 | channel << 8
+// | first strip); then one lane per digi finds the record it belongs to (the last marker at or
+// before it: a ballot of the marker bits, carried across steps) and writes its digi word. The
+// list's other slots never carry bit 31: the digi words use bits 0-27, and the kernel clears
+// the list before its first tile. From global memory (a FED larger than the stage): one lane
+// per channel expands its runs, four ADC bytes per iteration.
+template <bool kStaged, class P, int W, int DW>
 __device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, uint32_t* dl, P src,
                                          uint32_t c0, uint32_t c1) {
     const uint32_t b0 = sm.ch_base[c0 + w];
-    for (uint32_t ch = c0 + lane(); ch < c1; ch += kWave) {
-        if (sm.ch_st[ch] & SC_CH_MALFORMED) continue;
-        const uint32_t p = sm.ch_pos[ch];
-        const uint32_t len = sm.ch_len[ch];
-        uint32_t o = sm.ch_base[ch + w] - b0;
-        uint32_t q = 0;
-        while (q < len) {
-            const uint32_t first = src[p + q], cnt = src[p + q + 1];
-            const uint32_t base = (ch << 16) | (first << 8);
-            const uint32_t s = p + q + 2;
-            uint32_t i = 0;
-            for (; i + 4 <= cnt; i += 4) {
-                const uint32_t a0 = src[s + i], a1 = src[s + i + 1], a2 = src[s + i + 2],
-                               a3 = src[s + i + 3];
-                dl[o + i] = base + (i << 8) + a0;
-                dl[o + i + 1] = base + ((i + 1) << 8) + a1;
-                dl[o + i + 2] = base + ((i + 2) << 8) + a2;
-                dl[o + i + 3] = base + ((i + 3) << 8) + a3;
+    if constexpr (kStaged) {
+        static_assert(TileSmem<W, DW>::kStageBytes + 16 <= (1 << 13), "marker source offsets are 13 bits");
+        for (uint32_t ch = c0 + lane(); ch < c1; ch += kWave) {
+            if (sm.ch_st[ch] & SC_CH_MALFORMED) continue;
+            const uint32_t p = sm.ch_pos[ch];
+            const uint32_t len = sm.ch_len[ch];
+            uint32_t o = sm.ch_base[ch + w] - b0;
+            uint32_t q = 0;
+            while (q < len) {
+                const uint32_t first = src[p + q], cnt = src[p + q + 1];
+                dl[o] = 0x80000000u | ((p + q + 2) << 15) | (ch << 8) | first;
+                o += cnt;
+                q += 2 + cnt;
             }
-            for (; i < cnt; ++i) dl[o + i] = base + (i << 8) + src[s + i];
-            o += cnt;
-            q += 2 + cnt;
+        }
+        wave_sync();
+        const uint32_t n = uni(sm.ch_base[c1 + w] - b0);
+        const uint64_t upto = lane() == kWave - 1 ? ~0ull : (2ull << lane()) - 1ull;
+        uint32_t carry_m = 0u, carry_j = 0u;   // the last marker seen and its slot (uniform)
+        for (uint32_t j0 = 0; j0 < n; j0 += kWave) {
+            const uint32_t j = j0 + lane();
+            const uint32_t v = j < n ? dl[j] : 0u;
+            const uint64_t heads = __ballot((v >> 31) != 0u);
+            const uint64_t mine = heads & upto;
+            const uint32_t hl = mine ? 63u - (uint32_t)__clzll((long long)mine) : 0u;
+            const uint32_t hv = __shfl(v, (int)hl);
+            const uint32_t m = mine ? hv : carry_m;
+            const uint32_t k = j - (mine ? j0 + hl : carry_j);
+            const uint32_t so = (m >> 15) & 0x1fffu, first = m & 0xffu, ch = (m >> 8) & 0x7fu;
+            if (j < n) dl[j] = (ch << 16) | ((first + k) << 8) | src[so + k];
+            if (heads) {
+                const uint32_t last = 63u - (uint32_t)__clzll((long long)heads);
+                carry_m = uni(__shfl(v, (int)last));
+                carry_j = j0 + last;
+            }
+        }
+    } else {
+        for (uint32_t ch = c0 + lane(); ch < c1; ch += kWave) {
+            if (sm.ch_st[ch] & SC_CH_MALFORMED) continue;
+            const uint32_t p = sm.ch_pos[ch];
+            const uint32_t len = sm.ch_len[ch];
+            uint32_t o = sm.ch_base[ch + w] - b0;
+            uint32_t q = 0;
+            while (q < len) {
+                const uint32_t first = src[p + q], cnt = src[p + q + 1];
+                const uint32_t base = (ch << 16) | (first << 8);
+                const uint32_t s = p + q + 2;
+                uint32_t i = 0;
+                for (; i + 4 <= cnt; i += 4) {
+                    const uint32_t a0 = src[s + i], a1 = src[s + i + 1], a2 = src[s + i + 2],
+                                   a3 = src[s + i + 3];
+                    dl[o + i] = base + (i << 8) + a0;
+                    dl[o + i + 1] = base + ((i + 1) << 8) + a1;
+                    dl[o + i + 2] = base + ((i + 2) << 8) + a2;
+                    dl[o + i + 3] = base + ((i + 3) << 8) + a3;
+                }
+                for (; i < cnt; ++i) dl[o + i] = base + (i << 8) + src[s + i];
+                o += cnt;
+                q += 2 + cnt;
+            }
         }
     }
     wave_sync();
@@ -1045,8 +1089,8 @@ __device__ void zs_tile(const FusedArgs& A, TileSmem<W, DW>& sm, uint32_t e, uin
     const bool fits = wk.fits != 0;
     const uint32_t delta = wk.delta;
     auto build = [&](uint32_t c0, uint32_t c1) {
-        if (fits) build_zs(sm, w, dl, (const uint8_t*)(sm.stage + delta), c0, c1);
-        else      build_zs(sm, w, dl, gc(g), c0, c1);
+        if (fits) build_zs<true>(sm, w, dl, (const uint8_t*)(sm.stage + delta), c0, c1);
+        else      build_zs<false>(sm, w, dl, gc(g), c0, c1);
     };
     cluster_group(A, sm, ev, e, f, w, n_chunks, build);
 }
@@ -1118,6 +1162,8 @@ __device__ __forceinline__ void run_tiles(TileSmem<W, DW>& sm, uint32_t* queue, 
 template <int W, int DW>
 __global__ __launch_bounds__(kWave * W) void fused_kernel(FusedArgs A) {
     __shared__ TileSmem<W, DW> sm;
+    // the ZS build finds its record markers by bit 31 of the digi list's slots: clear them once
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(W * DW); i += kWave * W) sm.digi[i] = 0u;
     run_tiles(sm, A.queue, A.n_ev, A.cal.n_fed, A.fed_major,
               [&](uint32_t e, uint32_t f) { zs_tile<W, DW>(A, sm, e, f); });
 }
