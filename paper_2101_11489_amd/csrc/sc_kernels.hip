@@ -276,6 +276,9 @@ __device__ WalkResult stage_and_walk(TileSmem<W, DW>& sm, const uint8_t* g, uint
         const uint32_t delta = stage_bytes<kWave * W>(sm, threadIdx.x, g, L, gains);
         tile_sync();
         if (wave_index<W>() == 0u) {
+            // the walk is a serial chain that the tile's other waves wait for at the next
+            // barrier: its wave issues ahead of the CU's other waves meanwhile
+            __builtin_amdgcn_s_setprio(3);
             // lane k (mod 64) keeps channel k's record position and length. Branch-free steps
             // whose serial chain is only read, add, clamp: a record fits the FED when the next
             // position is <= L, and since positions only grow, the records that fit come first
@@ -305,6 +308,7 @@ __device__ WalkResult stage_and_walk(TileSmem<W, DW>& sm, const uint8_t* g, uint
             sm.walk[0] = good;
             sm.walk[1] = (good == (uint32_t)kNch && pos < L) ? 1u : 0u;
             sm.walk[2] = delta;
+            __builtin_amdgcn_s_setprio(0);
         }
     } else {
         // larger than the stage: wave 0 stages windows of the FED in turn and walks them; the
@@ -1137,7 +1141,11 @@ __device__ __forceinline__ uint32_t next_tile(TileSmem<W, DW>& sm, uint32_t* que
         return uni(atomicAdd(queue, lane() == 0u ? 1u : 0u));
     } else {
         // wave 0 rewrites walk[3] only after the barrier that ends the tile: one barrier here
-        if (wave_index<W>() == 0u) sm.walk[3] = uni(atomicAdd(queue, lane() == 0u ? 1u : 0u));
+        if (wave_index<W>() == 0u) {
+            __builtin_amdgcn_s_setprio(3);   // the tile's waves wait for this ticket
+            sm.walk[3] = uni(atomicAdd(queue, lane() == 0u ? 1u : 0u));
+            __builtin_amdgcn_s_setprio(0);
+        }
         tile_sync();
         return uni(sm.walk[3]);
     }
