@@ -434,6 +434,7 @@ __device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, uint32
     const uint32_t b0 = sm.ch_base[c0 + w];
     if constexpr (kStaged) {
         static_assert(TileSmem<W, DW>::kStageBytes + 16 <= (1 << 13), "marker source offsets are 13 bits");
+        __builtin_amdgcn_s_setprio(2);   // a serial pass that the digi pass waits for
         for (uint32_t ch = c0 + lane(); ch < c1; ch += kWave) {
             if (sm.ch_st[ch] & SC_CH_MALFORMED) continue;
             const uint32_t p = sm.ch_pos[ch];
@@ -447,6 +448,7 @@ __device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, uint32
                 q += 2 + cnt;
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         wave_sync();
         const uint32_t n = uni(sm.ch_base[c1 + w] - b0);
         const uint64_t upto = lane() == kWave - 1 ? ~0ull : (2ull << lane()) - 1ull;
@@ -464,7 +466,7 @@ __device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, uint32
             if (j < n) dl[j] = (ch << 16) | ((first + k) << 8) | src[so + k];
             if (heads) {
                 const uint32_t last = 63u - (uint32_t)__clzll((long long)heads);
-                carry_m = uni(__shfl(v, (int)last));
+                carry_m = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)last);
                 carry_j = j0 + last;
             }
         }
