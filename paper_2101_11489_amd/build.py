@@ -14,10 +14,13 @@ INCLUDE = os.path.join(ROOT, "include")
 ARCH = os.environ.get("SC_OFFLOAD_ARCH", "gfx950")
 
 # Device code: no FP contraction (the one fused step is an explicit fmaf), correctly rounded FP32
-# division and square root, and no packed-FP32 instructions.
+# division and square root, and no packed-FP32 instructions. Atomics whose operand differs across
+# the lanes (the tile queue: 1 from lane 0, 0 from the others) are reduced across the wavefront
+# with DPP before the one atomic, instead of a loop over the active lanes.
 DEVICE_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
                 "-fhip-fp32-correctly-rounded-divide-sqrt", "-Xclang", "-target-feature",
-                "-Xclang", "-packed-fp32-ops", "-Wall", "-I", INCLUDE, "-I", CSRC]
+                "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP",
+                "-Wall", "-I", INCLUDE, "-I", CSRC]
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-x", "c++", "-D__HIP_PLATFORM_AMD__",
               "-I", os.path.join(ROCM, "include"), "-I", INCLUDE, "-I", CSRC]

@@ -51,6 +51,7 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));   // two digi words
 
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
 __device__ __forceinline__ uint64_t mask_lt() { return (1ull << lane()) - 1ull; }
+__device__ __forceinline__ uint64_t mask_le() { return mask_lt() | (1ull << lane()); }
 __device__ __forceinline__ uint32_t popc(uint64_t m) { return (uint32_t)__popcll(m); }
 __device__ __forceinline__ uint32_t uni(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
@@ -65,9 +66,48 @@ template <class T> __device__ __forceinline__ T* uniptr(T* p) {
 __device__ __forceinline__ uint32_t last_lane(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
 }
+// Lane i receives lane i-1's value (lane 0 receives 0): DPP wave_shr:1.
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);
+}
+// Lane i receives lane i+1's value (lane 63 receives 0): DPP wave_shl:1.
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);
+}
+
+// Sums along the runs of a 64-digi step: lane i adds the values of the r lanes just below it
+// (the part of its run that lies in the step; r = 0 outside runs), whatever the run lengths, in
+// six DPP steps: Hillis-Steele inside rows of 16 lanes (row_shr 1, 2, 4, 8; lanes whose source
+// lies in the row before read 0), then the carries across rows (row_bcast:15 into rows 1 and 3,
+// row_bcast:31 into rows 2 and 3), each taken only by lanes whose run began before the row.
 template <int Ctrl, int RowMask>
 __device__ __forceinline__ uint32_t dpp_in(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, RowMask, 0xf, true);
+}
+__device__ __forceinline__ uint32_t as_bits(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ uint32_t as_bits(uint32_t x) { return x; }
+__device__ __forceinline__ void add_if(float& x, uint32_t y, bool c) {
+    x = c ? x + __uint_as_float(y) : x;
+}
+__device__ __forceinline__ void add_if(uint32_t& x, uint32_t y, bool c) { x = c ? x + y : x; }
+
+template <int Ctrl, int RowMask, class A, class B>
+__device__ __forceinline__ void run_sum_step(A& a, B& b, bool c) {
+    const uint32_t ya = dpp_in<Ctrl, RowMask>(as_bits(a));
+    const uint32_t yb = dpp_in<Ctrl, RowMask>(as_bits(b));
+    add_if(a, ya, c);
+    add_if(b, yb, c);
+}
+
+template <class A, class B>
+__device__ __forceinline__ void run_sums(A& a, B& b, uint32_t r) {
+    const uint32_t l = lane(), lr = l & 15u;
+    run_sum_step<0x111, 0xf>(a, b, r >= 1u);
+    run_sum_step<0x112, 0xf>(a, b, r >= 2u);
+    run_sum_step<0x114, 0xf>(a, b, r >= 4u);
+    run_sum_step<0x118, 0xf>(a, b, r >= 8u);
+    run_sum_step<0x142, 0xa>(a, b, (l & 16u) != 0u && r > lr);
+    run_sum_step<0x143, 0xc>(a, b, l >= 32u && r + 32u > l);
 }
 
 // Inclusive sum over the wavefront in six DPP steps: row_shr 1, 2, 4, 8 inside rows of 16 lanes,
@@ -116,9 +156,15 @@ __device__ __forceinline__ unsigned long long pack_state(uint64_t flag, uint32_t
     return (flag << 62) | ((uint64_t)(ncl & 0x7fffffffu) << 31) | (uint64_t)(nadc & 0x7fffffffu);
 }
 
-// Digi word (first word of a list slot, before the cluster decisions): adc(8) | strip(8) |
-// channel-in-FED(7); (channel, strip) is the strip's index in the FED.
+// Digi word in the list: adc(8) | strip(8) | channel-in-FED(7), and after forming the flags
+// active | seed | continues-previous | accepted | undecided (the last two on the first digi of a
+// run: accepted, or left to the sequential noise sum).
+constexpr uint32_t kActBit = 1u << 23, kSeedBit = 1u << 24, kContBit = 1u << 25,
+                   kAccBit = 1u << 26, kRedoBit = 1u << 27;
+constexpr uint32_t kNoKey = 0xffffffffu;
 __device__ __forceinline__ uint32_t d_adc(uint32_t d) { return d & 255u; }
+__device__ __forceinline__ uint32_t d_strip(uint32_t d) { return (d >> 8) & 255u; }
+__device__ __forceinline__ uint32_t d_ch(uint32_t d) { return (d >> 16) & 127u; }
 __device__ __forceinline__ uint32_t d_pos(uint32_t d) { return (d >> 8) & 0x7fffu; }
 
 // The little-endian u16 at byte o of a 4-byte aligned LDS buffer, from the two aligned words
@@ -134,7 +180,7 @@ struct TileSmem {
     static constexpr int kStageBytes = 6656;   // a FED of full-detector events at 5 % occupancy
     static constexpr int kStageData = kStageBytes - 16;   // FED bytes that fit (alignment slack)
     alignas(16) uint8_t stage[kStageBytes + 16];         // the FED's bytes (+ readable pad)
-    u32x2 slot[W * DW];           // digi list of wave w: [w*DW, (w+1)*DW), two words per digi
+    uint32_t digi[W * DW];                               // wave w: [w*DW, (w+1)*DW)
     alignas(16) float gain[2 * kNch];                    // the FED's APV gains
     uint32_t ch_pos[2 * kWave];   // 96 used; 128 so that two full-wave stores fit
     uint16_t ch_len[2 * kWave];
@@ -145,8 +191,8 @@ struct TileSmem {
     uint32_t grp_cnt[W + 1][3];   // per group: clusters, member ADCs; [W]: the FED's offsets
 };
 
-// Two-wave tiles of 2048 digis fit six to a CU (160 KiB of LDS).
-static_assert(sizeof(TileSmem<2, 1024>) <= 160 * 1024 / 6, "six two-wave tiles per CU");
+// Two-wave tiles of 2880 digis fit eight to a CU (160 KiB of LDS).
+static_assert(sizeof(TileSmem<2, 1440>) <= 160 * 1024 / 8, "eight two-wave tiles per CU");
 
 // Workgroup barrier (every wave of the tile passes it); a no-op for single-wave tiles.
 __device__ __forceinline__ void tile_sync() { __syncthreads(); }
@@ -374,22 +420,20 @@ __device__ uint32_t plan_chunks(TileSmem<W, DW>& sm, uint32_t w, uint32_t c_lo, 
     return n_chunks;
 }
 
-// Expand the records of channels [c0, c1) into the digi list sl (first words).
+// Expand the records of channels [c0, c1) into the digi list dl.
 // From the staged FED (LDS) in two passes: one lane per channel writes, at the first digi slot
 // of each of its records, a marker (bit 31 | source offset of the ADC bytes << 15 | channel << 8
 // | first strip); then one lane per digi finds the record it belongs to (the last marker at or
 // before it: a ballot of the marker bits, carried across steps) and writes its digi word. The
-// list's first words are cleared before the markers are written (digi words use bits 0-22). From global memory (a FED larger than the stage): one lane
+// list's other slots never carry bit 31: the digi words use bits 0-27, and the kernel clears
+// the list before its first tile. From global memory (a FED larger than the stage): one lane
 // per channel expands its runs, four ADC bytes per iteration.
 template <bool kStaged, class P, int W, int DW>
-__device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, u32x2* sl, P src,
+__device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, uint32_t* dl, P src,
                                          uint32_t c0, uint32_t c1) {
     const uint32_t b0 = sm.ch_base[c0 + w];
     if constexpr (kStaged) {
         static_assert(TileSmem<W, DW>::kStageBytes + 16 <= (1 << 13), "marker source offsets are 13 bits");
-        const uint32_t n = uni(sm.ch_base[c1 + w] - b0);
-        for (uint32_t j = lane(); j < n; j += kWave) sl[j].x = 0u;
-        wave_sync();
         __builtin_amdgcn_s_setprio(2);   // a serial pass that the digi pass waits for
         for (uint32_t ch = c0 + lane(); ch < c1; ch += kWave) {
             if (sm.ch_st[ch] & SC_CH_MALFORMED) continue;
@@ -399,18 +443,19 @@ __device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, u32x2*
             uint32_t q = 0;
             while (q < len) {
                 const uint32_t first = src[p + q], cnt = src[p + q + 1];
-                sl[o].x = 0x80000000u | ((p + q + 2) << 15) | (ch << 8) | first;
+                dl[o] = 0x80000000u | ((p + q + 2) << 15) | (ch << 8) | first;
                 o += cnt;
                 q += 2 + cnt;
             }
         }
         __builtin_amdgcn_s_setprio(0);
         wave_sync();
+        const uint32_t n = uni(sm.ch_base[c1 + w] - b0);
         const uint64_t upto = lane() == kWave - 1 ? ~0ull : (2ull << lane()) - 1ull;
         uint32_t carry_m = 0u, carry_j = 0u;   // the last marker seen and its slot (uniform)
         for (uint32_t j0 = 0; j0 < n; j0 += kWave) {
             const uint32_t j = j0 + lane();
-            const uint32_t v = j < n ? sl[j].x : 0u;
+            const uint32_t v = j < n ? dl[j] : 0u;
             const uint64_t heads = __ballot((v >> 31) != 0u);
             const uint64_t mine = heads & upto;
             const uint32_t hl = mine ? 63u - (uint32_t)__clzll((long long)mine) : 0u;
@@ -418,7 +463,7 @@ __device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, u32x2*
             const uint32_t m = mine ? hv : carry_m;
             const uint32_t k = j - (mine ? j0 + hl : carry_j);
             const uint32_t so = (m >> 15) & 0x1fffu, first = m & 0xffu, ch = (m >> 8) & 0x7fu;
-            if (j < n) sl[j].x = (ch << 16) | ((first + k) << 8) | src[so + k];
+            if (j < n) dl[j] = (ch << 16) | ((first + k) << 8) | src[so + k];
             if (heads) {
                 const uint32_t last = 63u - (uint32_t)__clzll((long long)heads);
                 carry_m = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)last);
@@ -440,12 +485,12 @@ __device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, u32x2*
                 for (; i + 4 <= cnt; i += 4) {
                     const uint32_t a0 = src[s + i], a1 = src[s + i + 1], a2 = src[s + i + 2],
                                    a3 = src[s + i + 3];
-                    sl[o + i].x = base + (i << 8) + a0;
-                    sl[o + i + 1].x = base + ((i + 1) << 8) + a1;
-                    sl[o + i + 2].x = base + ((i + 2) << 8) + a2;
-                    sl[o + i + 3].x = base + ((i + 3) << 8) + a3;
+                    dl[o + i] = base + (i << 8) + a0;
+                    dl[o + i + 1] = base + ((i + 1) << 8) + a1;
+                    dl[o + i + 2] = base + ((i + 2) << 8) + a2;
+                    dl[o + i + 3] = base + ((i + 3) << 8) + a3;
                 }
-                for (; i < cnt; ++i) sl[o + i].x = base + (i << 8) + src[s + i];
+                for (; i < cnt; ++i) dl[o + i] = base + (i << 8) + src[s + i];
                 o += cnt;
                 q += 2 + cnt;
             }
@@ -456,7 +501,7 @@ __device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, u32x2*
 
 // Dense rows of channels [c0, c1) -> digi list; 4 channels per wave step, 16 lanes x 16 strips.
 template <int W, int DW>
-__device__ __forceinline__ void build_dense(TileSmem<W, DW>& sm, uint32_t w, u32x2* sl,
+__device__ __forceinline__ void build_dense(TileSmem<W, DW>& sm, uint32_t w, uint32_t* dl,
                                             const uint8_t* rows, uint32_t c0, uint32_t c1) {
     const uint32_t b0 = sm.ch_base[c0 + w];
     for (uint32_t cb = c0; cb < c1; cb += 4) {
@@ -476,7 +521,7 @@ __device__ __forceinline__ void build_dense(TileSmem<W, DW>& sm, uint32_t w, u32
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const uint32_t a = (wds[k >> 2] >> ((k & 3) * 8)) & 255u;
-                if (a) sl[o++].x = base + ((uint32_t)k << 8) + a;
+                if (a) dl[o++] = base + ((uint32_t)k << 8) + a;
             }
         }
     }
@@ -502,160 +547,366 @@ __device__ __forceinline__ uint32_t count_dense_row(const uint8_t* row) {
     return cnt;
 }
 
-// ---- calibrated strip values into the list ---------------------------------------------------
-// The effective noise of every digi of sl[0, nd) into its second word, one lane per digi with the
-// gathers of kBatch steps in flight. Consecutive digis lie on nearby strips, so a step's loads
-// touch few cache lines; the lane-sequential pass below then reads the noise from LDS.
-__device__ __forceinline__ void gather_noise(u32x2* sl, uint32_t nd, gconst<float>* noise) {
-    constexpr int kBatch = 8;
-    for (uint32_t b = 0; b < nd; b += kBatch * kWave) {
-        float n[kBatch];
-#pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            const uint32_t j = b + (uint32_t)k * kWave + lane();
-            n[k] = j < nd ? noise[d_pos(sl[j].x)] : 0.0f;
-        }
-#pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            const uint32_t j = b + (uint32_t)k * kWave + lane();
-            if (j < nd) sl[j].y = __float_as_uint(n[k]);
-        }
-    }
-    wave_sync();
+// ---- cluster forming, digi-parallel -------------------------------------------------------
+// Uniform state of the run still open at the last digi of the previous step.
+struct OpenRun {
+    uint32_t key;   // position + 1 of its last digi (kNoKey: no open run)
+    uint32_t head;  // digi index of its first digi
+    uint32_t rp;    // run position of its last digi
+    float S;        // noise sum so far in tree order (steers the cluster-threshold filter)
+    uint32_t Q;     // raw ADC sum | seed count << 16
+    uint32_t mark;  // its threshold decision as it stands (valid if it ends here): a head bit
+};
+
+// Cluster threshold of the runs ending at their lanes (§2: charge against the cluster
+// threshold): accepted when seeded and (float)Q >= t * sqrtf(S), S summed by fmaf from the run's
+// first strip. St, the same sum taken in tree order by run_sums, is within (L + 35) roundings of
+// the exact sum, as the sequential one is within L (L = rp + 1 strips; every path through the
+// tree has at most 35 additions and products for a run of at most 256 strips). So wherever
+// q >= r (1 + e) or q < r (1 - e), with r = t * sqrt(St) and e = (L + 64) * 2^-24, the
+// sequential sum decides the same way. Returns the head bit: kAccBit (accepted), kRedoBit (too
+// close to call: settle_runs decides from the sequential sum) or 0.
+__device__ __forceinline__ uint32_t cluster_mark(bool end, uint32_t rp, uint32_t Q, float St,
+                                                 float t) {
+    const bool seeded = end && (Q >> 16) != 0u;
+    const float q = (float)(Q & 0xffffu);
+    const float r = t * __builtin_amdgcn_sqrtf(St);
+    const float e = (float)(rp + 65u) * 0x1p-24f;
+    const bool in_range = St >= 0x1p-60f && St <= 0x1p100f;   // false for NaN
+    const bool yes = in_range && q >= r * (1.0f + e);
+    const bool no = in_range && q < r * (1.0f - e);
+    return !seeded ? 0u : yes ? kAccBit : no ? 0u : kRedoBit;
 }
 
-// ---- cluster decisions, lane-sequential ---------------------------------------------------
-// Gain-corrected ADC: min(rint(adc / gain), 65535) with the FP32 quotient.
-__device__ __forceinline__ uint32_t corrected_adc(uint32_t a, float g) {
-    const float q = __builtin_rintf((float)a / g);
-    return q > 65535.0f ? 65535u : (uint32_t)q;
+// The runs marked kRedoBit in dl[0, nd): their threshold from the sequential fmaf sum of the
+// noise squares from the first strip, as the definition has it (rare; one lane per run).
+__device__ void settle_runs(uint32_t* dl, uint32_t nd, gconst<float>* noise, float t,
+                            uint32_t& n_cl, uint32_t& my_adc) {
+    for (uint32_t base = 0; base < nd; base += kWave) {
+        const uint32_t j = base + lane();
+        const uint32_t d = j < nd ? dl[j] : 0u;
+        bool acc = false;
+        uint32_t width = 0;
+        if (d & kRedoBit) {
+            float S = 0.0f;
+            uint32_t Q = 0, i = j, w = d;
+            for (;;) {
+                const float ni = noise[d_pos(w)];
+                S = __builtin_fmaf(ni, ni, S);
+                Q += d_adc(w);
+                if (++i >= nd) break;
+                w = dl[i];
+                if (!(w & kContBit)) break;
+            }
+            width = i - j;
+            acc = (float)Q >= t * __builtin_sqrtf(S);
+            if (acc) dl[j] = d | kAccBit;
+        }
+        if (acc) my_adc += width;
+        n_cl += popc(__ballot(acc));
+    }
 }
 
-// §2's three thresholds over the digi list sl[0, nd) (w0 = digi word, w1 = effective noise), in
-// the definition's own order: lane l scans the digis of [l*K, (l+1)*K) (K = ceil(nd/64)) one
-// after the other, exactly as a sequential scan would, and so sums the noise squares of a run
-// left to right with fmaf. A run belongs to the lane holding its first digi: a lane first skips
-// the digis that continue a run from before its range (it reads the digi before its range to
-// tell), and finishes its last run past the end of its range. Each digi's outputs are written by
-// its run's owner, in place (a lane only writes digis it has read, and reads a digi in an earlier
-// step than any other lane writes it):
-//   w0 <- c | strip << 16 | channel << 24 | continues-previous << 31   (c: gain-corrected ADC)
-//   w1 of the last digi of a run <- C | (width - 1) << 24 when accepted (C = sum c < 2^24), else
-//      kEndNone; w1 of the first digi of an accepted run of width >= 2 <- M = sum strip * c.
-// An inactive digi is a run of its own that is never accepted. Returns this lane's accepted
-// clusters and member digis.
-constexpr uint32_t kEndNone = 0xffffffffu;   // the code of a run end that is no cluster
+// Runs of a step of 128 digis, two per lane: digi A of lane l sits at position 2l, B at 2l + 1.
+// Digi A of lane 0 heads the part of its run that lies in the step. Run positions count from the
+// run's first digi, across steps too (carry: run position + 1 of the previous step's last digi).
+struct PairRuns {
+    uint32_t rpA, rpB;   // run positions of A and B
+    bool fromA;          // A's run began in an earlier step
+    uint32_t lanes;      // lanes back to where the run of B starts (0 when B is inactive)
+};
+__device__ __forceinline__ PairRuns pair_runs(bool actA, bool contA, bool actB, bool contB,
+                                              bool cont0, uint32_t carry) {
+    const uint32_t l = lane();
+    const bool hA = actA && (!contA || l == 0u);
+    const bool hB = actB && !contB;
+    // nearest head at or below A: heads A of lanes <= l (position 2j), heads B of lanes < l (2j+1)
+    const uint64_t ha = __ballot(hA) & mask_le(), hb = __ballot(hB) & mask_lt();
+    const uint32_t qa = ha ? 2u * (63u - (uint32_t)__clzll((long long)ha)) + 1u : 0u;
+    const uint32_t qb = hb ? 2u * (63u - (uint32_t)__clzll((long long)hb)) + 2u : 0u;
+    const uint32_t headA = (qa > qb ? qa : qb) - 1u;
+    const uint32_t lrpA = actA ? 2u * l - headA : 0u;
+    const uint32_t lrpB = contB ? lrpA + 1u : 0u;
+    PairRuns r;
+    r.fromA = actA && cont0 && headA == 0u;
+    r.rpA = lrpA + (r.fromA ? carry : 0u);
+    r.rpB = lrpB + ((contB && r.fromA) ? carry : 0u);
+    // the run of B starts in lane l when B heads it or continues an A that heads it
+    const uint64_t sb = __ballot(hB || (contB && hA)) & mask_le();
+    r.lanes = actB ? l - (sb ? 63u - (uint32_t)__clzll((long long)sb) : 0u) : 0u;
+    return r;
+}
 
-__device__ __forceinline__ void decide_pass(u32x2* sl, uint32_t nd, const float* gain,
-                                            const DeviceCalib& cal, uint32_t& lane_cl,
-                                            uint32_t& lane_adc) {
-    const uint32_t K = (nd + kWave - 1) / kWave;
-    const uint32_t s = lane() * K;
-    const uint32_t e = s + K < nd ? s + K : nd;
-    uint32_t ncl = 0, nadc = 0;
-    if (s < nd) {   // no cross-lane operation inside: each lane runs its own scan
-        bool own = s == 0u;   // owning runs (false while skipping a run from before s)
-        bool pact = false;    // previous digi active
-        uint32_t pkey1 = kEndNone;   // previous digi's (channel, strip) + 1
-        if (!own) {
-            const u32x2 p = sl[s - 1u];
-            pact = (float)d_adc(p.x) > cal.t_channel * __uint_as_float(p.y);
-            pkey1 = d_pos(p.x) + 1u;
-        }
-        // the open run: first digi h, width w (0: none), seeded, sums of noise squares (in
-        // order), raw ADC, gain-corrected ADC and strip * corrected ADC
-        bool sd = false;
-        uint32_t h = 0, w = 0, Q = 0, C = 0, M = 0;
-        float S = 0.0f;
-        // Straight-line steps (selects, predicated stores): digi nd is a virtual inactive digi
-        // that ends the last run.
-        for (uint32_t j = s;; ++j) {
-            u32x2 v = {0u, 0u};
-            if (j < nd) v = sl[j];
-            const uint32_t a = d_adc(v.x), key = d_pos(v.x), strip = key & 255u;
-            const float n = __uint_as_float(v.y), af = (float)a;
-            const bool act = j < nd && af > cal.t_channel * n;
-            const bool seed = af > cal.t_seed * n;
-            const bool cont = act && pact && key == pkey1 && strip != 0u;
-            const bool stop = j >= e && (!own || !cont);
-            // the owned run ending at digi j-1: the cluster threshold and its codes
-            const bool closing = w != 0u && !cont;
-            const bool acc =
-                closing && sd && (float)Q >= cal.t_cluster * __builtin_sqrtf(S);
-            if (closing) sl[j - 1u].y = acc ? (C | ((w - 1u) << 24)) : kEndNone;
-            if (acc && w > 1u) sl[h].y = M;
-            ncl += acc ? 1u : 0u;
-            nadc += acc ? w : 0u;
-            if (stop) break;
-            own = own || !cont;
-            const uint32_t c = corrected_adc(a, gain[key >> 7]);
-            S = __builtin_fmaf(n, n, cont ? S : 0.0f);
-            Q = (cont ? Q : 0u) + a;
-            sd = (cont && sd) || (act && seed);
-            C = (cont ? C : 0u) + c;
-            M = (cont ? M : 0u) + strip * c;
-            h = cont ? h : j;
-            w = act && own ? (cont ? w + 1u : 1u) : 0u;
-            if (own) sl[j] = u32x2{c | (key << 16) | (cont ? 0x80000000u : 0u), act ? v.y : kEndNone};
-            pact = act;
-            pkey1 = key + 1u;
+// One step of 128 digis [base, base+128) of the list dl, two per lane: lane l holds digis
+// A = base + 2l and B = A + 1. Flags, runs, cluster threshold; every lane takes part (no divergent
+// cross-lane work). Adds the flag bits to the digi words, marks accepted run heads and counts
+// clusters / member ADCs.
+__device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t nd, uint32_t dA,
+                                          uint32_t dB, float nA, float nB, const DeviceCalib& cal,
+                                          OpenRun& open, uint32_t& n_cl, uint32_t& my_adc,
+                                          uint32_t& pending) {
+    const uint32_t l = lane();
+    const uint32_t jA = base + 2u * l, jB = jA + 1u;
+    const bool vA = jA < nd, vB = jB < nd;
+    const uint32_t aA = d_adc(dA), aB = d_adc(dB);
+    const uint32_t pA = d_pos(dA), pB = d_pos(dB);
+    const float afA = (float)aA, afB = (float)aB;
+    const bool actA = vA && afA > cal.t_channel * nA;
+    const bool actB = vB && afB > cal.t_channel * nB;
+    const bool sdA = actA && afA > cal.t_seed * nA;
+    const bool sdB = actB && afB > cal.t_seed * nB;
+    // continues the previous digi: both active, same channel, adjacent strips (B follows A in
+    // the lane, A follows the previous lane's B)
+    const uint32_t keyA = actA ? pA + 1u : kNoKey;
+    const uint32_t keyB = actB ? pB + 1u : kNoKey;
+    const bool contB = actB && d_strip(dB) != 0u && keyA == pB;
+    uint32_t pk = from_prev_lane(keyB);
+    pk = l == 0u ? open.key : pk;
+    const bool contA = actA && d_strip(dA) != 0u && pk == pA;
+    const bool cont0 = (__ballot(contA) & 1ull) != 0ull;
+    // the run open at the end of the previous step ends before this step
+    if (open.key != kNoKey && !cont0 && open.mark) {
+        dl[open.head] |= open.mark;   // same word, same value from every lane
+        if (open.mark == kAccBit) {
+            n_cl += 1;
+            my_adc += l == 0u ? open.rp + 1u : 0u;
+        } else {
+            pending += 1;
         }
     }
-    lane_cl = ncl;
-    lane_adc = nadc;
+    const PairRuns pr = pair_runs(actA, contA, actB, contB, cont0, open.rp + 1u);
+    const uint32_t rpA = pr.rpA, rpB = pr.rpB;
+    // sums along the runs: noise squares (tree order), raw charge, seeds. Each lane's share of
+    // the run of its digi B is summed across lanes; digi A takes the previous lane's total.
+    float SA = actA ? nA * nA : 0.0f, SB = actB ? nB * nB : 0.0f;
+    uint32_t QA = actA ? aA + (sdA ? 0x10000u : 0u) : 0u;
+    uint32_t QB = actB ? aB + (sdB ? 0x10000u : 0u) : 0u;
+    if (cont0) {
+        const bool l0 = l == 0u;
+        SA = l0 ? SA + open.S : SA;
+        QA = l0 ? QA + open.Q : QA;
+    }
+    SB = contB ? SB + SA : SB;
+    QB = contB ? QB + QA : QB;
+    run_sums(SB, QB, pr.lanes);
+    {
+        const float Sp = __uint_as_float(from_prev_lane(__float_as_uint(SB)));
+        const uint32_t Qp = from_prev_lane(QB);
+        const bool in = contA && l != 0u;
+        SA = in ? SA + Sp : SA;
+        QA = in ? QA + Qp : QA;
+    }
+    if (vA) dl[jA] = dA | (actA ? kActBit : 0u) | (sdA ? kSeedBit : 0u) | (contA ? kContBit : 0u);
+    if (vB) dl[jB] = dB | (actB ? kActBit : 0u) | (sdB ? kSeedBit : 0u) | (contB ? kContBit : 0u);
+    // runs that end inside this step; the run at digi B of lane 63 may go on, so it stays open
+    // with its threshold decision as it stands
+    const bool next_contA = from_next_lane(contA ? 1u : 0u) != 0u;
+    const bool endA = actA && !contB;
+    const bool endB = actB && !next_contA;
+    const uint32_t markA = cluster_mark(endA, rpA, QA, SA, cal.t_cluster);
+    const uint32_t markB = cluster_mark(endB, rpB, QB, SB, cal.t_cluster);
+    const bool eB = markB != 0u && l != 63u;
+    if (markA) dl[jA - rpA] |= markA;
+    if (eB) dl[jB - rpB] |= markB;
+    const bool accA = markA == kAccBit, accB = eB && markB == kAccBit;
+    my_adc += (accA ? rpA + 1u : 0u) + (accB ? rpB + 1u : 0u);
+    n_cl += popc(__ballot(accA)) + popc(__ballot(accB));
+    pending += popc(__ballot(markA == kRedoBit)) + popc(__ballot(eB && markB == kRedoBit));
+    open.key = last_lane(keyB);
+    open.rp = last_lane(rpB);
+    open.head = base + 127u - open.rp;
+    open.S = __uint_as_float(last_lane(__float_as_uint(SB)));
+    open.Q = last_lane(QB);
+    open.mark = last_lane(markB);
+}
+
+// Forming over the digi list dl[0, nd): steps of 128 digis, the loads of kBatch steps in flight.
+__device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const DeviceCalib& cal,
+                                          uint32_t fed, uint32_t& n_cl, uint32_t& n_adc) {
+    constexpr int kBatch = 4;
+    constexpr uint32_t kStep = 2 * kWave;
+    gconst<float>* noise = gc(cal.noise) + fed * kStripsPerFed;
+    OpenRun open{kNoKey, 0u, 0u, 0.0f, 0u, 0u};
+    uint32_t ncl = 0, my_adc = 0, pending = 0;
+    for (uint32_t b = 0; b < nd; b += kBatch * kStep) {
+        uint32_t dA[kBatch], dB[kBatch];
+        float nA[kBatch], nB[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const uint32_t j = b + (uint32_t)k * kStep + 2u * lane();
+            u32x2 w = {0u, 0u};
+            if (j < nd) w = *reinterpret_cast<const u32x2*>(dl + j);   // dl + j + 1 is inside the list
+            dA[k] = w.x;
+            dB[k] = j + 1u < nd ? w.y : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const uint32_t j = b + (uint32_t)k * kStep + 2u * lane();
+            nA[k] = j < nd ? noise[d_pos(dA[k])] : 0.0f;
+            nB[k] = j + 1u < nd ? noise[d_pos(dB[k])] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const uint32_t base = b + (uint32_t)k * kStep;
+            if (base < nd)
+                form_step(dl, base, nd, dA[k], dB[k], nA[k], nB[k], cal, open, ncl, my_adc,
+                          pending);
+        }
+    }
+    if (open.key != kNoKey && open.mark) {
+        dl[open.head] |= open.mark;
+        if (open.mark == kAccBit) {
+            ncl += 1;
+            my_adc += lane() == 0u ? open.rp + 1u : 0u;
+        } else {
+            pending += 1;
+        }
+    }
+    if (pending) {
+        wave_sync();
+        settle_runs(dl, nd, noise, cal.t_cluster, ncl, my_adc);
+    }
+    n_cl = ncl;
+    n_adc = wave_sum(my_adc);
     wave_sync();
 }
 
 // ---- outputs ------------------------------------------------------------------------------
-// Member ADCs and cluster records of the decided list sl[0, nd) at their final positions
-// ([base_cl, base_cl + n_cl), [base_adc, base_adc + n_adc) in the event's outputs), one lane per
-// digi, 64 digis per step, from the last step to the first. A digi ends its run when the next
-// one does not continue it; a run end with an accepted code carries a cluster, and the members
-// are the digis linked to an accepted end through continue bits: a fill from each accepted end
-// towards lower lanes, done on the ballot masks (bit-reversed, a carry through each run's chain
-// of links, one accepted end per chain). Positions count back from the ends of the ranges.
-__device__ __forceinline__ void copy_out(const u32x2* sl, uint32_t nd, uint32_t fed,
-                                         const EventDesc& ev, uint32_t base_cl, uint32_t n_cl,
-                                         uint32_t base_adc, uint32_t n_adc) {
+// Uniform state of the member run still open at the last digi of the previous write step.
+struct OpenCluster {
+    uint32_t open;   // 1: the last digi of the previous step was a member
+    uint32_t acc;    // acceptance of that digi's run (for the digis that continue it)
+    uint32_t rp;     // run position of that digi
+    uint32_t C, M;   // sums of c and strip*c so far
+    u32x4 rec;       // its record as it stands (valid if the cluster ends there)
+};
+
+__device__ __forceinline__ u32x4 make_record(uint32_t fed, uint32_t dw, uint32_t rp, uint32_t C,
+                                             uint32_t M) {
+    const uint32_t strip = d_strip(dw);
+    const uint32_t first = strip - rp, width = rp + 1u;
+    // barycenter: sum (s+1/2) c / sum c = (2M + C) / (2C), numerator and denominator exact
+    const float bary = C ? (float)((2.0 * (double)M + (double)C) / (2.0 * (double)C))
+                         : (float)first + (float)width * 0.5f;
+    return u32x4{fed * kNch + d_ch(dw), first | (width << 16), C, __float_as_uint(bary)};
+}
+
+// Gain-corrected ADC of a member digi: min(rint(adc / gain), 65535) with the FP32 quotient.
+__device__ __forceinline__ uint32_t corrected_adc(uint32_t d, float g) {
+    const float q = __builtin_rintf((float)d_adc(d) / g);
+    return q > 65535.0f ? 65535u : (uint32_t)q;
+}
+
+// Records and member ADCs of the digi list dl[0, nd) at their final positions, 128 digis per
+// step, two per lane (A = base + 2l, B = A + 1) as in forming. The member ADCs are
+// gain-corrected here.
+template <int W, int DW>
+__device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint32_t* dl,
+                                           uint32_t nd, uint32_t fed, const EventDesc& ev,
+                                           uint32_t base_cl, uint32_t base_adc) {
+    constexpr uint32_t kStep = 2 * kWave;
     gmut<uint16_t>* adc_out = gm(ev.adc);
     gmut<u32x4>* cl_out = gm(reinterpret_cast<u32x4*>(ev.cl));
-    uint32_t rem_cl = n_cl, rem_adc = n_adc;
-    uint64_t carry_mem = 0, carry_k = 0;   // digi 64 of the step: member, continues digi 63
-    for (uint32_t b = (nd + kWave - 1) / kWave * kWave; b > 0;) {
-        b -= kWave;
-        const uint32_t j = b + lane();
-        const bool valid = j < nd;
-        u32x2 v = {0u, kEndNone};
-        if (valid) v = sl[j];
-        const uint64_t vb = __ballot(valid);
-        const uint64_t kb = __ballot(valid && (v.x >> 31) != 0u);
-        const uint64_t link = (kb >> 1) | (carry_k << 63);   // bit i: digi i+1 continues digi i
-        const uint64_t acc = vb & ~link & __ballot(v.y != kEndNone);
-        const uint64_t ra = __builtin_bitreverse64(acc), rl = __builtin_bitreverse64(link);
-        const uint64_t seeds = (ra << 1) | carry_mem;
-        const uint64_t mem = __builtin_bitreverse64(ra | (rl & ~(rl + seeds))) & vb;
-        carry_mem = mem & 1ull;
-        carry_k = kb & 1ull;
-        rem_adc -= popc(mem);
-        rem_cl -= popc(acc);
-        const uint64_t me = 1ull << lane();
-        if (mem & me) {
-            const uint32_t p = base_adc + rem_adc + popc(mem & mask_lt());
-            if (p < ev.cap_adc) adc_out[p] = (uint16_t)(v.x & 0xffffu);
+    OpenCluster oc{0u, 0u, 0u, 0u, 0u, u32x4{0u, 0u, 0u, 0u}};
+    uint32_t rc = base_cl, pa = base_adc;
+    const uint32_t l = lane();
+    // the digi words and APV gains of the next step are read while this step runs
+    auto gain_of = [&](uint32_t d) { return sm.gain[2 * d_ch(d) + (d_strip(d) >> 7)]; };
+    auto load = [&](uint32_t j, uint32_t& dA, uint32_t& dB) {
+        u32x2 w = {0u, 0u};
+        if (j < nd) w = *reinterpret_cast<const u32x2*>(dl + j);   // dl + j + 1 is inside the list
+        dA = w.x;
+        dB = j + 1u < nd ? w.y : 0u;
+    };
+    uint32_t nA, nB;
+    load(2u * l, nA, nB);
+    float gnA = gain_of(nA), gnB = gain_of(nB);
+    for (uint32_t base = 0; base < nd; base += kStep) {
+        const uint32_t dA = nA, dB = nB;
+        const float gA = gnA, gB = gnB;
+        load(base + kStep + 2u * l, nA, nB);
+        const bool actA = (dA & kActBit) != 0u, actB = (dB & kActBit) != 0u;
+        const bool contA = (dA & kContBit) != 0u, contB = (dB & kContBit) != 0u;
+        const bool cont0 = (__ballot(contA) & 1ull) != 0ull;
+        // the cluster open at the end of the previous step is complete unless lane 0 continues it
+        if (oc.open && !cont0) {
+            if (rc < ev.cap_cl) cl_out[rc] = oc.rec;   // same record from every lane
+            rc += 1;
         }
-        if (acc & me) {
-            const uint32_t width = (v.y >> 24) + 1u, C = v.y & 0xffffffu;
-            const uint32_t strip = (v.x >> 16) & 255u, ch = (v.x >> 24) & 127u;
-            const uint32_t first = strip + 1u - width;
-            const uint32_t M = width == 1u ? strip * (v.x & 0xffffu) : sl[j + 1u - width].y;
-            // barycenter: sum (s+1/2) c / sum c = (2M + C) / (2C), numerator and denominator exact
-            const float bary = C ? (float)((2.0 * (double)M + (double)C) / (2.0 * (double)C))
-                                 : (float)first + (float)width * 0.5f;
-            const uint32_t p = base_cl + rem_cl + popc(acc & mask_lt());
-            if (p < ev.cap_cl)
-                cl_out[p] = u32x4{fed * kNch + ch, first | (width << 16), C, __float_as_uint(bary)};
+        const PairRuns pr = pair_runs(actA, contA, actB, contB, cont0, oc.rp + 1u);
+        const uint32_t rpA = pr.rpA, rpB = pr.rpB;
+        // members: active digis whose run head carries the accepted bit; the head of A's run
+        // sits rpA positions back (in an earlier step when fromA)
+        const uint64_t abA = __ballot(actA && !contA && (dA & kAccBit));
+        const uint64_t abB = __ballot(actB && !contB && (dB & kAccBit));
+        const uint32_t headA = 2u * l - (actA ? rpA : 0u);
+        const bool accA = pr.fromA ? (oc.acc != 0u)
+                                   : ((((headA & 1u) ? abB : abA) >> (headA >> 1)) & 1ull) != 0ull;
+        const bool memA = actA && accA;
+        const bool memB = actB && (contB ? accA : ((abB >> l) & 1ull) != 0ull);
+        uint32_t cA = 0, cB = 0;
+        if (memA) cA = corrected_adc(dA, gA);
+        if (memB) cB = corrected_adc(dB, gB);
+        const uint64_t mbA = __ballot(memA), mbB = __ballot(memB);
+        {
+            const uint32_t p = pa + popc(mbA & mask_lt()) + popc(mbB & mask_lt());
+            if (memA && p < ev.cap_adc) adc_out[p] = (uint16_t)cA;
+            const uint32_t q = p + (memA ? 1u : 0u);
+            if (memB && q < ev.cap_adc) adc_out[q] = (uint16_t)cB;
         }
+        pa += popc(mbA) + popc(mbB);
+        // charge and strip-weighted charge along member runs: each lane's share of the run of
+        // its digi B is summed across lanes; digi A takes the previous lane's total
+        uint32_t CA = cA, MA = d_strip(dA) * cA;
+        if (cont0 && oc.open) {
+            const bool l0 = l == 0u;
+            CA = l0 ? CA + oc.C : CA;
+            MA = l0 ? MA + oc.M : MA;
+        }
+        uint32_t CB = cB + (contB ? CA : 0u), MB = d_strip(dB) * cB + (contB ? MA : 0u);
+        run_sums(CB, MB, pr.lanes);
+        {
+            const uint32_t Cp = from_prev_lane(CB), Mp = from_prev_lane(MB);
+            const bool in = contA && l != 0u;
+            CA = in ? CA + Cp : CA;
+            MA = in ? MA + Mp : MA;
+        }
+        // records of the clusters ending in this step (A before B in a lane); the record of
+        // digi B of lane 63 as it stands is kept for the next step, which stores it if the
+        // cluster does not go on
+        const bool next_contA = from_next_lane(contA ? 1u : 0u) != 0u;
+        const bool endA = memA && !contB;
+        const bool endB = memB && !next_contA;
+        const bool eB = endB && l != 63u;
+        // one record per lane first (A's where A ends, else B's), B's too where both end
+        u32x4 rec1 = {0u, 0u, 0u, 0u}, recB = {0u, 0u, 0u, 0u};
+        if (endA || endB) {
+            rec1 = make_record(fed, endA ? dA : dB, endA ? rpA : rpB, endA ? CA : CB,
+                               endA ? MA : MB);
+        }
+        const bool both = endA && endB;
+        if (__ballot(both) != 0ull) {
+            if (both) recB = make_record(fed, dB, rpB, CB, MB);
+        }
+        if (!endA) recB = rec1;
+        const uint64_t ebA = __ballot(endA), ebB = __ballot(eB);
+        {
+            const uint32_t p = rc + popc(ebA & mask_lt()) + popc(ebB & mask_lt());
+            if (endA && p < ev.cap_cl) cl_out[p] = rec1;
+            const uint32_t q = p + (endA ? 1u : 0u);
+            if (eB && q < ev.cap_cl) cl_out[q] = recB;
+        }
+        rc += popc(ebA) + popc(ebB);
+        oc.open = (uint32_t)(mbB >> 63);
+        oc.acc = (uint32_t)((__ballot(memB) >> 63) & 1ull);
+        oc.rp = last_lane(rpB);
+        oc.C = last_lane(CB);
+        oc.M = last_lane(MB);
+        oc.rec = u32x4{last_lane(recB.x), last_lane(recB.y), last_lane(recB.z), last_lane(recB.w)};
+        gnA = gain_of(nA);
+        gnB = gain_of(nB);
     }
+    if (oc.open && rc < ev.cap_cl) cl_out[rc] = oc.rec;
     wave_sync();
 }
 
@@ -734,25 +985,15 @@ __device__ void cluster_group(const FusedArgs& A, TileSmem<W, DW>& sm, const Eve
                               BuildFn build) {
     const uint32_t n_fed = A.cal.n_fed;
     unsigned long long* row = A.tile_state + (size_t)e * n_fed;
-    u32x2* sl = sm.slot + w * DW;
+    uint32_t* dl = sm.digi + w * DW;
     const uint8_t* cf = sm.chunk_first[w];
-    gconst<float>* noise = gc(A.cal.noise) + (size_t)f * kStripsPerFed;
-    // the cluster decisions of channels [c0, c1): returns the chunk's digi count, its clusters
-    // and member ADCs in cl / adc (uniform)
-    auto decide = [&](uint32_t c0, uint32_t c1, uint32_t& cl, uint32_t& adc) {
-        build(c0, c1);
-        const uint32_t nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
-        gather_noise(sl, nd, noise);
-        uint32_t lcl, ladc;
-        decide_pass(sl, nd, sm.gain, A.cal, lcl, ladc);
-        cl = wave_sum(lcl);
-        adc = wave_sum(ladc);
-        return nd;
-    };
     // counts: one pass over each chunk; the last chunk stays in the list for its writes
     uint32_t n_cl = 0, n_adc = 0, last_cl = 0, last_adc = 0, last_nd = 0;
     for (uint32_t ci = 0; ci < n_chunks; ++ci) {
-        last_nd = decide(uni(cf[ci]), uni(cf[ci + 1]), last_cl, last_adc);
+        const uint32_t c0 = uni(cf[ci]), c1 = uni(cf[ci + 1]);
+        build(c0, c1);
+        last_nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
+        form_pass(dl, last_nd, A.cal, f, last_cl, last_adc);
         n_cl += last_cl;
         n_adc += last_adc;
     }
@@ -786,15 +1027,18 @@ __device__ void cluster_group(const FusedArgs& A, TileSmem<W, DW>& sm, const Eve
         ex_adc = uni(sm.grp_cnt[W][1]);
         err = uni(sm.grp_cnt[W][2]);
     }
-    // writes: the last chunk first (still decided in the list), then the earlier chunks of a
-    // chunked group, built and decided again
+    // writes: the last chunk first (still formed in the list), then the earlier chunks of a
+    // chunked group, built and formed again
     const uint32_t bc = ex_cl + pre_cl, ba = ex_adc + pre_adc;
-    copy_out(sl, last_nd, f, ev, bc + n_cl - last_cl, last_cl, ba + n_adc - last_adc, last_adc);
+    write_pass(sm, dl, last_nd, f, ev, bc + n_cl - last_cl, ba + n_adc - last_adc);
     uint32_t oc = bc, oa = ba;
     for (uint32_t ci = 0; ci + 1 < n_chunks; ++ci) {
+        const uint32_t c0 = uni(cf[ci]), c1 = uni(cf[ci + 1]);
+        build(c0, c1);
+        const uint32_t nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
         uint32_t ccl, cadc;
-        const uint32_t nd = decide(uni(cf[ci]), uni(cf[ci + 1]), ccl, cadc);
-        copy_out(sl, nd, f, ev, oc, ccl, oa, cadc);
+        form_pass(dl, nd, A.cal, f, ccl, cadc);
+        write_pass(sm, dl, nd, f, ev, oc, oa);
         oc += ccl;
         oa += cadc;
     }
@@ -847,12 +1091,12 @@ __device__ void zs_tile(const FusedArgs& A, TileSmem<W, DW>& sm, uint32_t e, uin
                                [&](uint32_t ch) { return check_channel(sm, gg, ch, wk); }, total);
     }
     emit_status(sm, c_lo, c_hi, ev.chan_status, f, &A.res[e].flags);
-    u32x2* sl = sm.slot + w * DW;
+    uint32_t* dl = sm.digi + w * DW;
     const bool fits = wk.fits != 0;
     const uint32_t delta = wk.delta;
     auto build = [&](uint32_t c0, uint32_t c1) {
-        if (fits) build_zs<true>(sm, w, sl, (const uint8_t*)(sm.stage + delta), c0, c1);
-        else      build_zs<false>(sm, w, sl, gc(g), c0, c1);
+        if (fits) build_zs<true>(sm, w, dl, (const uint8_t*)(sm.stage + delta), c0, c1);
+        else      build_zs<false>(sm, w, dl, gc(g), c0, c1);
     };
     cluster_group(A, sm, ev, e, f, w, n_chunks, build);
 }
@@ -881,8 +1125,8 @@ __device__ void dense_tile(const FusedArgs& A, TileSmem<W, DW>& sm, const uint8_
     const uint32_t n_chunks = plan_chunks(
         sm, w, c_lo, c_hi,
         [&](uint32_t ch) { return count_dense_row(rows + ch * kStripsPerChannel); }, total);
-    u32x2* sl = sm.slot + w * DW;
-    auto build = [&](uint32_t c0, uint32_t c1) { build_dense(sm, w, sl, rows, c0, c1); };
+    uint32_t* dl = sm.digi + w * DW;
+    auto build = [&](uint32_t c0, uint32_t c1) { build_dense(sm, w, dl, rows, c0, c1); };
     cluster_group(A, sm, ev, 0, f, w, n_chunks, build);
 }
 
@@ -928,6 +1172,8 @@ __device__ __forceinline__ void run_tiles(TileSmem<W, DW>& sm, uint32_t* queue, 
 template <int W, int DW>
 __global__ __launch_bounds__(kWave * W) void fused_kernel(FusedArgs A) {
     __shared__ TileSmem<W, DW> sm;
+    // the ZS build finds its record markers by bit 31 of the digi list's slots: clear them once
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(W * DW); i += kWave * W) sm.digi[i] = 0u;
     run_tiles(sm, A.queue, A.n_ev, A.cal.n_fed, A.fed_major,
               [&](uint32_t e, uint32_t f) { zs_tile<W, DW>(A, sm, e, f); });
 }
@@ -961,7 +1207,7 @@ __global__ __launch_bounds__(kWave) void unpack_kernel(const uint8_t* zs, const 
     }
     emit_status(sm, 0u, (uint32_t)kNch, chan_status, f, &res->flags);
     // 16 channels at a time: zero rows in LDS, expand records, copy out with 16-byte stores
-    uint8_t* rowbuf = reinterpret_cast<uint8_t*>(sm.slot);   // 4 KiB of the 8 KiB list
+    uint8_t* rowbuf = reinterpret_cast<uint8_t*>(sm.digi);   // 4 KiB
     gmut<u32x4>* out = gm(reinterpret_cast<u32x4*>(dense + (size_t)f * kStripsPerFed));
     for (uint32_t g0 = 0; g0 < (uint32_t)kNch; g0 += 16) {
         for (uint32_t i = lane(); i < 16 * kStripsPerChannel / 4; i += kWave)
