@@ -156,21 +156,26 @@ typedef struct {
 
 void sc_default_options(sc_options *opt);
 
-/* Create a context on opt->device: validates and uploads the calibration, derives the per-strip
- * integer thresholds, allocates workspaces. *out is NULL on failure. */
+/* Create a context on opt->device: validates the calibration and uploads it once (§2: calibration
+ * unpacked per FED channel, here kept resident for every later event); on the device it derives
+ * one FP32 effective noise per strip (the noise itself, or +inf for an unusable strip, which then
+ * never passes ADC > t*noise) and keeps the per-APV gains. Allocates the first workspaces. *out is
+ * NULL on failure. */
 sc_status sc_create(const sc_calib *calib, const sc_options *opt, sc_ctx **out);
 
 /* Destroy a context: stops the server (pending tickets are dropped), frees everything. */
 void sc_destroy(sc_ctx *ctx);
 
 /* §2 unpacking step alone: ZS event -> dense ADCs (u8 [n_fed*96*256], 0 where no ADC was
- * recorded) and optional chan_status (u8 [n_fed*96]); outputs in memory kind out_mem.
- * Returns SC_OK or SC_MALFORMED when done. */
+ * recorded) and optional chan_status (u8 [n_fed*96]); both outputs lie in memory kind out_mem
+ * (SC_MEM_HOST or SC_MEM_DEVICE; any other value is SC_ERR_INVALID_ARG, checked before anything
+ * else). Returns SC_OK or SC_MALFORMED when done. */
 sc_status sc_unpack(sc_ctx *ctx, const sc_event *ev, uint8_t *adc_dense, uint8_t *chan_status,
                     sc_mem out_mem);
 
-/* §2 clustering step alone, from dense ADCs (u8 [n_fed*96*256] in memory kind in_mem).
- * out->chan_status is ignored. sc_unpack + sc_cluster is the plain per-event GPU path.
+/* §2 clustering step alone, from dense ADCs (u8 [n_fed*96*256] in memory kind in_mem:
+ * SC_MEM_HOST or SC_MEM_DEVICE, any other value is SC_ERR_INVALID_ARG). out->chan_status is
+ * ignored. sc_unpack + sc_cluster is the plain per-event GPU path.
  * Returns SC_OK, or SC_ERR_OVERFLOW with the needed sizes in out. */
 sc_status sc_cluster(sc_ctx *ctx, const uint8_t *adc_dense, sc_mem in_mem, sc_clusters *out);
 
@@ -182,17 +187,19 @@ sc_status sc_cluster(sc_ctx *ctx, const uint8_t *adc_dense, sc_mem in_mem, sc_cl
 sc_status sc_process_events(sc_ctx *ctx, const sc_event *ev, uint32_t n, sc_clusters *out,
                             sc_status *ev_status);
 
-/* Serving. sc_submit admits one event into the server's queue (starting the server thread on
- * first use) and returns a ticket. Host ZS bytes are copied before the call returns; device ZS
+/* Serving (§3: several events in flight at once, their transfers overlapped with computation).
+ * sc_submit admits one event into the server's queue (starting the server thread on first use)
+ * and returns a ticket. Host ZS bytes are copied before the call returns; device ZS
  * buffers and every output buffer must stay valid until sc_poll returns a final status. Events
  * that arrive while others run join the next batch as soon as a stream slot and HBM budget are
  * free (continuous batching). Returns SC_OK, SC_ERR_AGAIN (queue full), SC_ERR_BUDGET (can never
  * fit) or SC_ERR_INVALID_ARG. */
 sc_status sc_submit(sc_ctx *ctx, const sc_event *ev, sc_clusters *out, uint64_t *ticket);
 
-/* Wait up to timeout_us (0: do not wait, <0: forever) for a ticket. Returns SC_PENDING if not
- * finished, else the event's final status (as for sc_process_events), after which the ticket is
- * forgotten. */
+/* Completion side of the serving loop (§3: events processed concurrently, each collected when
+ * done). Wait up to timeout_us (0: do not wait, <0: forever) for a ticket. Returns SC_PENDING if
+ * not finished, else the event's final status (as for sc_process_events), after which the ticket
+ * is forgotten. */
 sc_status sc_poll(sc_ctx *ctx, uint64_t ticket, int64_t timeout_us);
 
 /* Open-loop load test of the server: submits n events at Poisson arrival times of mean rate

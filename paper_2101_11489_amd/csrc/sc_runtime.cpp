@@ -840,6 +840,8 @@ void sc_destroy(sc_ctx* c) {
 
 sc_status sc_unpack(sc_ctx* c, const sc_event* ev, uint8_t* adc_dense, uint8_t* chan_status,
                     sc_mem out_mem) {
+    if (out_mem != SC_MEM_HOST && out_mem != SC_MEM_DEVICE)
+        return fail(c, SC_ERR_INVALID_ARG, "sc_unpack: out_mem must be SC_MEM_HOST or SC_MEM_DEVICE");
     if (!c) return SC_ERR_INVALID_ARG;
     if (c->poisoned) return SC_ERR_DEVICE;
     if (!ev || !adc_dense) return fail(c, SC_ERR_INVALID_ARG, "NULL argument");
@@ -893,6 +895,8 @@ sc_status sc_unpack(sc_ctx* c, const sc_event* ev, uint8_t* adc_dense, uint8_t* 
 }
 
 sc_status sc_cluster(sc_ctx* c, const uint8_t* adc_dense, sc_mem in_mem, sc_clusters* out) {
+    if (in_mem != SC_MEM_HOST && in_mem != SC_MEM_DEVICE)
+        return fail(c, SC_ERR_INVALID_ARG, "sc_cluster: in_mem must be SC_MEM_HOST or SC_MEM_DEVICE");
     if (!c) return SC_ERR_INVALID_ARG;
     if (c->poisoned) return SC_ERR_DEVICE;
     if (!adc_dense || !out) return fail(c, SC_ERR_INVALID_ARG, "NULL argument");

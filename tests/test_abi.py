@@ -83,6 +83,23 @@ def test_create_without_gpu_fails_cleanly(built):
     assert built.sc_last_error(None)
 
 
+def test_unknown_memory_kinds_are_refused(built):
+    """sc_unpack and sc_cluster accept only SC_MEM_HOST and SC_MEM_DEVICE for the buffer they
+    name; anything else is refused before any other check (no device is touched)."""
+    import numpy as np
+    buf = np.zeros(64, dtype=np.uint8)
+    fo = np.zeros(2, dtype=np.uint64)
+    ev = sc.ScEvent(buf.ctypes.data, fo.ctypes.data, sc.SC_MEM_HOST)
+    for bad in (2, -1, 7):
+        rc = built.sc_unpack(None, ctypes.byref(ev), buf.ctypes.data, None, bad)
+        assert rc == sc.SC_ERR_INVALID_ARG
+        assert b"out_mem" in built.sc_last_error(None)
+        out = sc.ScClusters()
+        rc = built.sc_cluster(None, buf.ctypes.data, bad, ctypes.byref(out))
+        assert rc == sc.SC_ERR_INVALID_ARG
+        assert b"in_mem" in built.sc_last_error(None)
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(sc, "LIB_PATH", str(tmp_path / "nope.so"))
     monkeypatch.setattr(sc, "_lib", None)

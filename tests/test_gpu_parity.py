@@ -87,7 +87,6 @@ def test_cluster_dense_hand_channels():
         ref = oracle.cluster(dense, noise, gain, bad)
         with make_ctx(noise, gain, bad) as ctx:
             for device in (True, False):
-                out = ctx.output(*(max(ref.cl.size, 1),) * 2, device=device)
                 out = ctx.output(4096, 8192, device=device)
                 src = torch.from_numpy(dense).cuda() if device else dense
                 rc = ctx.cluster(src, out)
