@@ -152,7 +152,12 @@ typedef struct {
     double last_kernel_ms;   /* device time of the last fused/cluster launch (HIP events) */
     double kernel_ms_total;  /* sum of those device times over the timed launches */
     uint64_t kernels_timed;  /* number of launches summed in kernel_ms_total */
+    uint64_t allocations;    /* device and pinned-host allocations the library has made, in this
+                                process (all contexts) */
 } sc_stats;
+
+/* Limits of sc_process_events_static. */
+enum { SC_STATIC_MAX_EVENTS = 1024, SC_STATIC_MAX_TILES = 1024 * 440 };
 
 void sc_default_options(sc_options *opt);
 
@@ -186,6 +191,20 @@ sc_status sc_cluster(sc_ctx *ctx, const uint8_t *adc_dense, sc_mem in_mem, sc_cl
  * do not depend on the other events of the batch. */
 sc_status sc_process_events(sc_ctx *ctx, const sc_event *ev, uint32_t n, sc_clusters *out,
                             sc_status *ev_status);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): sc_process_events without any allocation. Every event
+ * and every output must be in device memory (SC_MEM_DEVICE; host kinds are SC_ERR_INVALID_ARG:
+ * they need staging, use sc_process_events), 1 <= n <= SC_STATIC_MAX_EVENTS and
+ * n * n_fed <= SC_STATIC_MAX_TILES, else SC_ERR_INVALID_ARG. The call's scratch (descriptors,
+ * look-back words, tile queue, per-event results) is one fixed array per GPU, about 3.7 MB, held
+ * from sc_create until the process ends and cleared by a fill kernel at the start of every call;
+ * descriptors and results pass through pinned host memory that sc_create allocated. All contexts
+ * on one GPU share that array: calls that overlap on one GPU (from different threads or
+ * contexts) race and must be serialised by the caller. Results, statuses and errors as for
+ * sc_process_events. */
+sc_status sc_process_events_static(sc_ctx *ctx, const sc_event *ev, uint32_t n, sc_clusters *out,
+                                   sc_status *ev_status);
 
 /* Serving (§3: several events in flight at once, their transfers overlapped with computation).
  * sc_submit admits one event into the server's queue (starting the server thread on first use)

@@ -23,6 +23,7 @@ STRIPS_PER_CHANNEL = 256
 
 SC_OK, SC_MALFORMED, SC_PENDING = 0, 1, 2
 SC_ERR_INVALID_ARG, SC_ERR_OVERFLOW, SC_ERR_BUDGET = -1, -2, -3
+SC_STATIC_MAX_EVENTS, SC_STATIC_MAX_TILES = 1024, 1024 * 440   # sc_process_events_static
 SC_ERR_AGAIN, SC_ERR_DEVICE, SC_ERR_NOMEM, SC_ERR_UNKNOWN_TICKET = -4, -5, -6, -7
 SC_MEM_HOST, SC_MEM_DEVICE = 0, 1
 CH_MALFORMED, CH_FED_TRAILING = 1, 2
@@ -34,7 +35,7 @@ CLUSTER_DTYPE = np.dtype([("channel", "<u4"), ("first", "<u2"), ("width", "<u2")
                           ("charge", "<u4"), ("barycenter", "<f4")])
 
 EXPORTED = ["sc_default_options", "sc_create", "sc_destroy", "sc_unpack", "sc_cluster",
-            "sc_process_events", "sc_submit", "sc_poll", "sc_serve_replay", "sc_get_tuning",
+            "sc_process_events", "sc_process_events_static", "sc_submit", "sc_poll", "sc_serve_replay", "sc_get_tuning",
             "sc_set_tuning", "sc_autotune", "sc_get_stats", "sc_last_error"]
 
 
@@ -79,7 +80,8 @@ class ScStats(ctypes.Structure):
                 ("graph_replays", ctypes.c_uint64), ("graph_captures", ctypes.c_uint64),
                 ("server_batches", ctypes.c_uint64), ("server_events", ctypes.c_uint64),
                 ("server_rejected_again", ctypes.c_uint64), ("last_kernel_ms", ctypes.c_double),
-                ("kernel_ms_total", ctypes.c_double), ("kernels_timed", ctypes.c_uint64)]
+                ("kernel_ms_total", ctypes.c_double), ("kernels_timed", ctypes.c_uint64),
+                ("allocations", ctypes.c_uint64)]
 
 
 _lib = None
@@ -102,6 +104,9 @@ def lib():
             "sc_cluster": ([P, P, ctypes.c_int, ctypes.POINTER(ScClusters)], st),
             "sc_process_events": ([P, ctypes.POINTER(ScEvent), ctypes.c_uint32,
                                    ctypes.POINTER(ScClusters), ctypes.POINTER(ctypes.c_int)], st),
+            "sc_process_events_static": ([P, ctypes.POINTER(ScEvent), ctypes.c_uint32,
+                                          ctypes.POINTER(ScClusters), ctypes.POINTER(ctypes.c_int)],
+                                         st),
             "sc_submit": ([P, ctypes.POINTER(ScEvent), ctypes.POINTER(ScClusters),
                            ctypes.POINTER(ctypes.c_uint64)], st),
             "sc_poll": ([P, ctypes.c_uint64, ctypes.c_int64], st),

@@ -51,6 +51,17 @@ struct FusedArgs {
     uint32_t fed_major;
 };
 
+// Scratch of the allocation-free batch call (sc_process_events_static), a file-scope device
+// array of sc_kernels.hip: per-event results, event descriptors, the tile queue and the
+// look-back words, for at most SC_STATIC_MAX_EVENTS events and SC_STATIC_MAX_TILES tiles.
+constexpr size_t kStaticResOff = 0;
+constexpr size_t kStaticDescOff = kStaticResOff + sizeof(EventResult) * SC_STATIC_MAX_EVENTS;
+constexpr size_t kStaticQueueOff = (kStaticDescOff + sizeof(EventDesc) * SC_STATIC_MAX_EVENTS + 255) / 256 * 256;
+constexpr size_t kStaticStateOff = kStaticQueueOff + 256;
+constexpr size_t kStaticScratchBytes = kStaticStateOff + sizeof(unsigned long long) * SC_STATIC_MAX_TILES;
+// Device address of that array on the current device (hipGetSymbolAddress; once per device).
+hipError_t static_scratch_address(void** ptr);
+
 // Launch helpers (sc_kernels.hip). All enqueue on `stream` and return the launch error.
 hipError_t launch_derive_calib(const float* noise, const float* gain, const uint8_t* bad,
                                uint32_t n_fed, float* noise_out, hipStream_t stream);

@@ -29,7 +29,16 @@
 
 #include "sc_internal.h"
 
+// The allocation-free batch call's scratch (layout in sc_internal.h). Host code must not use this
+// name as an address: it reaches the array through static_scratch_address().
+static __device__ __align__(256) unsigned char scratch[sc::kStaticScratchBytes];
+
 namespace sc {
+
+hipError_t static_scratch_address(void** ptr) {
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
 namespace {
 
 constexpr uint32_t kSpinLimit = 1u << 22;   // look-back wait bound (seconds of sleeping)

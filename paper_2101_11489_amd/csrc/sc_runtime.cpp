@@ -35,6 +35,9 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// Device and pinned-host allocations made by the library in this process (sc_stats.allocations).
+std::atomic<uint64_t> g_allocations{0};
+
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct DevBuf {
@@ -45,7 +48,10 @@ struct DevBuf {
         if (p) { (void)hipFree(p); p = nullptr; n = 0; }
         size_t want = align_up(std::max<size_t>(bytes, 256), 4096);
         hipError_t e = hipMalloc(&p, want);
-        if (e == hipSuccess) n = want;
+        if (e == hipSuccess) {
+            n = want;
+            g_allocations.fetch_add(1, std::memory_order_relaxed);
+        }
         return e;
     }
     void release() {
@@ -64,7 +70,10 @@ struct PinBuf {
         if (p) { (void)hipHostFree(p); p = nullptr; n = 0; }
         size_t want = align_up(std::max<size_t>(bytes, 256), 4096);
         hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
-        if (e == hipSuccess) n = want;
+        if (e == hipSuccess) {
+            n = want;
+            g_allocations.fetch_add(1, std::memory_order_relaxed);
+        }
         return e;
     }
     void release() {
@@ -144,9 +153,31 @@ struct sc_ctx {
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::unique_ptr<Server> server;
     std::mutex server_mu;
+    // sc_process_events_static: the device address of the per-GPU scratch array, and pinned
+    // host memory for its descriptors and results (both set up by sc_create)
+    uint8_t* d_static = nullptr;
+    PinBuf h_static;
 };
 
 namespace {
+
+// The address of the allocation-free call's scratch array on a device: asked for once per device,
+// with that device current (each GPU holds its own copy of the array).
+hipError_t static_scratch_for_device(int device, uint8_t** out) {
+    static std::mutex mu;
+    static std::map<int, uint8_t*> known;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = known.find(device);
+    if (it == known.end()) {
+        void* p = nullptr;
+        const hipError_t e = static_scratch_address(&p);   // the caller made `device` current
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        it = known.emplace(device, static_cast<uint8_t*>(p)).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
 
 sc_status fail(sc_ctx* c, sc_status st, const std::string& msg) {
     if (c) {
@@ -804,6 +835,7 @@ sc_status sc_create(const sc_calib* cal, const sc_options* opt_in, sc_ctx** out)
     if (e == hipSuccess) e = hipMalloc(&c->d_gain, sizeof(float) * n_apv);
     if (e == hipSuccess) e = hipMalloc(&d_noise_raw, sizeof(float) * n_strips);
     if (e == hipSuccess) e = hipMalloc(&d_bad, n_strips);
+    if (e == hipSuccess) g_allocations.fetch_add(4, std::memory_order_relaxed);
     if (e == hipSuccess) e = hipMemcpyAsync(d_noise_raw, cal->noise, sizeof(float) * n_strips, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->d_gain, cal->gain, sizeof(float) * n_apv, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d_bad, cal->bad, n_strips, hipMemcpyHostToDevice, c->stream);
@@ -813,6 +845,9 @@ sc_status sc_create(const sc_calib* cal, const sc_options* opt_in, sc_ctx** out)
     if (d_noise_raw) (void)hipFree(d_noise_raw);
     if (d_bad) (void)hipFree(d_bad);
     if (e == hipSuccess) e = c->ws.ensure_batch(64, c->n_fed);
+    if (e == hipSuccess) e = static_scratch_for_device(c->device, &c->d_static);
+    if (e == hipSuccess)
+        e = c->h_static.ensure((sizeof(EventDesc) + sizeof(EventResult)) * SC_STATIC_MAX_EVENTS);
     if (e != hipSuccess) {
         std::string msg = std::string("calibration upload: ") + hipGetErrorString(e);
         sc_destroy(c.release());
@@ -829,6 +864,7 @@ void sc_destroy(sc_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->ws.release();
+    c->h_static.release();
     if (c->d_noise) (void)hipFree(c->d_noise);
     if (c->d_gain) (void)hipFree(c->d_gain);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -955,6 +991,71 @@ sc_status sc_process_events(sc_ctx* c, const sc_event* ev, uint32_t n, sc_cluste
     }
     SC_HIP(c, hipSetDevice(c->device));
     return run_batch(c, ev, n, out, ev_status, all_device);
+}
+
+sc_status sc_process_events_static(sc_ctx* c, const sc_event* ev, uint32_t n, sc_clusters* out,
+                                   sc_status* ev_status) {
+    if (!c) return SC_ERR_INVALID_ARG;
+    if (c->poisoned) return SC_ERR_DEVICE;
+    if (!ev || !out) return fail(c, SC_ERR_INVALID_ARG, "NULL argument");
+    if (n == 0 || n > SC_STATIC_MAX_EVENTS)
+        return fail(c, SC_ERR_INVALID_ARG, "sc_process_events_static: n must be in 1..SC_STATIC_MAX_EVENTS");
+    if ((uint64_t)n * c->n_fed > SC_STATIC_MAX_TILES)
+        return fail(c, SC_ERR_INVALID_ARG,
+                    "sc_process_events_static: n * n_fed exceeds SC_STATIC_MAX_TILES");
+    EventDesc* hd = c->h_static.as<EventDesc>();
+    for (uint32_t i = 0; i < n; ++i) {
+        sc_status s = check_event(c, ev[i]);
+        if (s != SC_OK) return s;
+        s = check_out(c, out[i]);
+        if (s != SC_OK) return s;
+        if (ev[i].mem != SC_MEM_DEVICE || out[i].mem != SC_MEM_DEVICE)
+            return fail(c, SC_ERR_INVALID_ARG,
+                        "sc_process_events_static: events and outputs must be in device memory");
+        hd[i] = EventDesc{ev[i].zs, ev[i].fed_offset, out[i].cl, out[i].adc, out[i].chan_status,
+                          out[i].cap_cl, out[i].cap_adc};
+    }
+    SC_HIP(c, hipSetDevice(c->device));
+    FusedArgs a{};
+    a.ev = reinterpret_cast<const EventDesc*>(c->d_static + kStaticDescOff);
+    a.res = reinterpret_cast<EventResult*>(c->d_static + kStaticResOff);
+    a.tile_state = reinterpret_cast<unsigned long long*>(c->d_static + kStaticStateOff);
+    a.queue = reinterpret_cast<uint32_t*>(c->d_static + kStaticQueueOff);
+    a.cal.noise = c->d_noise;
+    a.cal.gain = c->d_gain;
+    a.cal.n_fed = c->n_fed;
+    a.cal.t_seed = c->t_seed;
+    a.cal.t_channel = c->t_channel;
+    a.cal.t_cluster = c->t_cluster;
+    a.n_ev = n;
+    a.fed_major = c->tuning.fed_major;
+    EventResult* hr = reinterpret_cast<EventResult*>(c->h_static.as<uint8_t>() +
+                                                     sizeof(EventDesc) * SC_STATIC_MAX_EVENTS);
+    hipStream_t s = c->stream;
+    SC_HIP(c, hipMemcpyAsync(const_cast<EventDesc*>(a.ev), hd, sizeof(EventDesc) * n,
+                             hipMemcpyHostToDevice, s));
+    // the array keeps the last call's contents: clear the look-back words, queue and results
+    SC_HIP(c, launch_reset(a, n * c->n_fed, s));
+    SC_HIP(c, hipEventRecord(c->ev0, s));
+    SC_HIP(c, launch_fused(a, c->tuning.tile_waves, c->tuning.chunk_digis,
+                           grid_for(c, n * c->n_fed, false), s));
+    SC_HIP(c, hipEventRecord(c->ev1, s));
+    SC_HIP(c, hipMemcpyAsync(hr, a.res, sizeof(EventResult) * n, hipMemcpyDeviceToHost, s));
+    SC_HIP(c, hipStreamSynchronize(s));
+    record_kernel_ms(c);
+    c->stats.launches++;
+    c->stats.events += n;
+    sc_status total = SC_OK;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (hr[i].flags & kResSpinTimeout)
+            return device_fail(c, hipErrorLaunchTimeOut, "fused kernel look-back wait bound");
+        out[i].n_cl = hr[i].n_cl;
+        out[i].n_adc = hr[i].n_adc;
+        const sc_status si = status_of(hr[i], out[i]);
+        if (ev_status) ev_status[i] = si;
+        total = worst(total, si);
+    }
+    return total;
 }
 
 sc_status sc_submit(sc_ctx* c, const sc_event* ev, sc_clusters* out, uint64_t* ticket) {
@@ -1164,6 +1265,7 @@ sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best
 sc_status sc_get_stats(const sc_ctx* c, sc_stats* s) {
     if (!c || !s) return SC_ERR_INVALID_ARG;
     *s = c->stats;
+    s->allocations = g_allocations.load(std::memory_order_relaxed);
     return SC_OK;
 }
 
