@@ -3,10 +3,18 @@
 
 Headline step: one fused, persistent launch (sc_process_events) over a batch of 64 synthetic
 full-detector events (440 FEDs x 96 channels x 256 strips each; per-event occupancy log-uniform in
-[0.5%, 5%]), inputs resident in HBM before the timed region, outputs written to HBM. Beside it:
-the plain per-event GPU path (sc_unpack then sc_cluster, one full-detector event at 1.5%
-occupancy per call), the same events through the fused kernel one at a time, and the oracle timed
-on host cores on a bounded sample.
+[0.5%, 5%]), in the batched workload's stated form: tile shape and order chosen by the library's
+autotuner on the batch, the launch replayed as a captured hipGraph; inputs resident in HBM before
+the timed region, outputs written to HBM. Beside it:
+  * the same batch launched eagerly, and eagerly with the caches (L2 and the Infinity Cache)
+    flushed by a 512 MiB write before every launch;
+  * measured read-stream and copy bandwidth of the box;
+  * the plain per-event GPU path (sc_unpack then sc_cluster) and the fused kernel one event at a
+    time, for the 50-FED and the full-detector single-event workloads (20 events each);
+  * the 256-event stress batch (6% occupancy, heavy width tail), first with output capacities
+    sized for the 64-event batch (it overflows), then again with the needed capacities;
+  * the serving sweep (Poisson arrivals at 20-120% of batched capacity);
+  * the oracle timed on host cores: one process, and one process per core of the box's share.
 
 Prints one JSON line. ``--gpus`` above 1 is refused: the path runs on one GPU.
 """
@@ -15,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import multiprocessing as mp
 import os
 import statistics
 import sys
@@ -30,6 +39,7 @@ import fedgen  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_kernel_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2101_11489_amd", "csrc", "sc_kernels.hip")
+STAGE_BYTES = 6640   # FED bytes the kernel's LDS stage holds; larger FEDs take the slow path
 
 
 def log(*a):
@@ -67,28 +77,265 @@ def load_traffic(n_launch_bytes_key):
     return t.get("hbm_bytes_per_launch")
 
 
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model
+
+
+# ---- the oracle on host cores -----------------------------------------------------------------
+_CPU_JOB = {}
+
+
+def _oracle_worker(args):
+    """Runs the oracle over events start, start+step, ... (cycling) for `seconds`; returns
+    (events done, seconds)."""
+    start, step, seconds = args
+    import oracle
+    events, cal, n_fed = _CPU_JOB["events"], _CPU_JOB["cal"], _CPU_JOB["n_fed"]
+    scratch = np.empty(n_fed * 96 * 256, np.uint8)
+    cl = np.empty(4_000_000, dtype=oracle.CLUSTER_DTYPE)
+    adc = np.empty(8_000_000, dtype=np.uint16)
+    done, k = 0, start
+    t0 = time.perf_counter()
+    while True:
+        e = events[k % len(events)]
+        oracle.process_event_raw(e.zs, e.fed_offset, cal.noise, cal.gain, cal.bad, scratch, cl, adc)
+        done += 1
+        k += step
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            return done, el
+
+
+def cpu_baseline(events, cal, n_fed, seconds, procs):
+    """The oracle (single-threaded C) on the batch's events: in this process, then in `procs`
+    forked processes at once (one event stream each, nothing shared). Runs before the GPU is
+    touched."""
+    _CPU_JOB.update(events=events, cal=cal, n_fed=n_fed)
+    done1, s1 = _oracle_worker((0, 1, seconds))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_oracle_worker, [(i, procs, seconds) for i in range(procs)])
+    agg = sum(d for d, _ in res) / max(s for _, s in res)
+    return {
+        "value": agg, "unit": "events/s", "cores": procs, "kind": "oracle",
+        "sample": f"the batch's {len(events)} events cycled for {seconds:.0f} s by each of {procs} "
+                  f"single-threaded oracle processes (one per core of the box's share; "
+                  f"{sum(d for d, _ in res)} events in total)",
+        "single_core_value": done1 / s1,
+        "single_core_sample": f"{done1} events in {s1:.1f} s, one process",
+        "cpu_model": host_cpu(), "host_cpus_visible": os.cpu_count(),
+    }
+
+
+# ---- GPU measurements ---------------------------------------------------------------------------
+def time_steps(ctx, batch, steps, warmup, stream, torch, graph, flush=None):
+    """K timed synchronous calls of the prepared batch (after W untimed ones). Returns wall time,
+    per-step latencies and the mean of the library's HIP-event kernel times (None when the
+    launch did not record them). flush: a tensor written (on the launch stream) before every
+    call, to empty the caches."""
+    ctx.tuning = {"use_graph": 1 if graph else 0}
+    for _ in range(warmup):
+        ctx.process_batch(batch)
+    torch.cuda.synchronize()
+    st0 = ctx.stats()
+    step_ms = []
+    kern = []
+    with torch.cuda.stream(stream):
+        t_start = time.perf_counter()
+        for k in range(steps):
+            if flush is not None:
+                flush.fill_(k & 0xff)
+                torch.cuda.synchronize()
+            ts = time.perf_counter()
+            ctx.process_batch(batch)
+            step_ms.append((time.perf_counter() - ts) * 1e3)
+            if flush is not None:
+                kern.append(ctx.stats()["last_kernel_ms"])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+    st1 = ctx.stats()
+    n_timed = st1["kernels_timed"] - st0["kernels_timed"]
+    kern_ms = None
+    if flush is not None:
+        kern_ms = statistics.mean(kern) if all(k > 0 for k in kern) else None
+    elif n_timed == steps:
+        kern_ms = (st1["kernel_ms_total"] - st0["kernel_ms_total"]) / n_timed
+    return {"elapsed_s": elapsed if flush is None else sum(step_ms) / 1e3, "step_ms": step_ms,
+            "kernel_ms": kern_ms}
+
+
+def stream_probe(torch, mib=2048, reps=10):
+    """Measured read-stream (a reduction over `mib` MiB) and copy bandwidth, GB/s."""
+    n = (mib << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn, moved in (("read_stream_gbs", lambda: x.sum(), n * 4),
+                            ("copy_gbs", lambda: y.copy_(x), 2 * n * 4)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = moved * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    out["bytes"] = mib << 20
+    return out
+
+
+def plain_line(sc, torch, stream, cfg_id, n_events, workers, tuning):
+    """The plain per-event path and the fused kernel per event and per batch on one workload."""
+    import oracle
+    cfg = fedgen.CONFIGS[cfg_id]
+    cal = fedgen.make_calibration(cfg)
+    evs = fedgen.make_events(cfg, cal, range(n_events), workers=workers)
+    ctx = sc.Context(cal.noise, cal.gain, cal.bad, device=0, stream=stream)
+    ctx.tuning = {k: tuning[k] for k in ("chunk_digis", "tile_waves", "tiles_per_cu", "fed_major")}
+    ctx.tuning = {"use_graph": 0}
+    d = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs]
+    o = [ctx.output(*sc.safe_caps(x)) for x in d]
+    dense = ctx.dense_buffer()
+    for x, y in zip(d[:2], o[:2]):   # warm-up of both paths
+        ctx.unpack(x, dense)
+        ctx.cluster(dense, y)
+        ctx.process_events([x], [y])
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        tp = time.perf_counter()
+        pk = []
+        for x, y in zip(d, o):
+            ctx.unpack(x, dense)
+            ku = ctx.stats()["last_kernel_ms"]
+            ctx.cluster(dense, y)
+            pk.append(ku + ctx.stats()["last_kernel_ms"])
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - tp
+        ref = oracle.process_event(evs[-1].zs, evs[-1].fed_offset, cal.noise, cal.gain, cal.bad)
+        cl, adc, _ = o[-1].to_numpy()
+        plain_ok = np.array_equal(cl, ref.cl) and np.array_equal(adc, ref.adc)
+        tf = time.perf_counter()
+        fk = []
+        for x, y in zip(d, o):
+            ctx.process_events([x], [y])
+            fk.append(ctx.stats()["last_kernel_ms"])
+        torch.cuda.synchronize()
+        single_s = time.perf_counter() - tf
+        cl, adc, _ = o[-1].to_numpy()
+        fused_ok = np.array_equal(cl, ref.cl) and np.array_equal(adc, ref.adc)
+        ctx.process_events(d, o)
+        tb = time.perf_counter()
+        bk = []
+        for _ in range(5):
+            ctx.process_events(d, o)
+            bk.append(ctx.stats()["last_kernel_ms"])
+        torch.cuda.synchronize()
+        batch_s = (time.perf_counter() - tb) / 5
+    b1 = algorithmic_bytes(evs, [(y.n_cl, y.n_adc) for y in o], cfg.n_fed)
+    ctx.close()
+    return {
+        "workload": f"{cfg.name}: {n_events} events of {cfg.n_fed} FEDs at "
+                    f"{cfg.occ * 100:.1f}% occupancy",
+        "plain_unpack_then_cluster_events_per_s": n_events / plain_s,
+        "plain_kernel_ms_per_event": statistics.mean(pk),
+        "fused_one_event_per_launch_events_per_s": n_events / single_s,
+        "fused_one_event_kernel_ms": statistics.mean(fk),
+        "fused_one_event_hbm_frac": (b1 / n_events) / (statistics.mean(fk) * 1e-3) / 1e9
+                                    / HBM_PEAK_GBS,
+        f"fused_batch_of_{n_events}_events_per_s": n_events / batch_s,
+        f"fused_batch_of_{n_events}_kernel_ms": statistics.mean(bk),
+        f"fused_batch_of_{n_events}_hbm_frac": b1 / (statistics.mean(bk) * 1e-3) / 1e9
+                                               / HBM_PEAK_GBS,
+        "parity": "bit-exact (last event, both paths)" if plain_ok and fused_ok else "MISMATCH",
+    }
+
+
+def stress_line(sc, torch, stream, workers, tuning, cap_cl, cap_adc, steps):
+    """The 256-event stress batch at full size: one launch with output capacities sized for the
+    64-event batch (overflows are reported with the needed sizes), then the batch again with
+    those sizes, timed."""
+    import oracle
+    cfg = fedgen.CONFIGS[4]
+    t0 = time.time()
+    cal = fedgen.make_calibration(cfg)
+    evs = fedgen.make_events(cfg, cal, range(cfg.n_events), workers=workers)
+    gen_s = time.time() - t0
+    sizes = np.concatenate([np.diff(e.fed_offset.astype(np.int64)) for e in evs])
+    ctx = sc.Context(cal.noise, cal.gain, cal.bad, device=0, stream=stream)
+    ctx.tuning = {k: tuning[k] for k in ("chunk_digis", "tile_waves", "tiles_per_cu", "fed_major")}
+    ctx.tuning = {"use_graph": 0}
+    d = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs]
+    o = [ctx.output(cap_cl, cap_adc) for _ in d]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        rc, sts = ctx.process_events(d, o)
+        first_ms = ctx.stats()["last_kernel_ms"]
+        torch.cuda.synchronize()
+    n_over = sum(1 for s in sts if s == sc.SC_ERR_OVERFLOW)
+    need = [(y.n_cl, y.n_adc) for y in o]
+    # retry with the needed sizes
+    o = [ctx.output(max(c, 1), max(a, 1)) for c, a in need]
+    batch = ctx.batch(d, o)
+    r = time_steps(ctx, batch, steps, 2, stream, torch, graph=False)
+    rc2 = ctx.process_batch(batch)[0]
+    torch.cuda.synchronize()
+    ok = True
+    for i in (0, len(evs) - 1):
+        ref = oracle.process_event(evs[i].zs, evs[i].fed_offset, cal.noise, cal.gain, cal.bad)
+        cl, adc, _ = o[i].to_numpy()
+        ok &= np.array_equal(cl, ref.cl) and np.array_equal(adc, ref.adc)
+    b = algorithmic_bytes(evs, [(y.n_cl, y.n_adc) for y in o], cfg.n_fed)
+    k = r["kernel_ms"]
+    ctx.close()
+    return {
+        "workload": f"stress: {len(evs)} events x {cfg.n_fed} FEDs at 6% occupancy, width "
+                    "1+Geometric(0.25) capped at 32, 1% bad strips, noise U[2,10]",
+        "generation_s": gen_s,
+        "zs_mb": sum(e.zs.size for e in evs) / 1e6,
+        "feds_larger_than_lds_stage": float(np.mean(sizes > STAGE_BYTES)),
+        "first_launch": {"capacities": [cap_cl, cap_adc], "status": rc,
+                         "events_overflowed": n_over, "kernel_ms": first_ms},
+        "retry": {"status": rc2, "events_per_s": len(evs) * steps / r["elapsed_s"],
+                  "ms_per_step": r["elapsed_s"] / steps * 1e3, "kernel_ms": k,
+                  "clusters": int(sum(c for c, _ in need)),
+                  "algorithmic_bytes_per_launch": b,
+                  "hbm_frac": (b / (k * 1e-3) / 1e9 / HBM_PEAK_GBS) if k else None},
+        "parity": "bit-exact (2 sampled events)" if ok else "MISMATCH",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--plain-events", type=int, default=8)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="CPU work the oracle baseline runs for (it stops after the event that "
-                         "crosses this time)")
-    ap.add_argument("--cpu-sample", type=int, default=8,
-                    help="at most this many passes over the batch for the CPU baseline")
+    ap.add_argument("--plain-events", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="seconds each oracle process of the CPU baseline runs for")
+    ap.add_argument("--cpu-procs", type=int, default=min(16, os.cpu_count() or 1),
+                    help="oracle processes of the CPU aggregate (the box's CPU share)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-stress", action="store_true")
+    ap.add_argument("--no-cold", action="store_true")
     ap.add_argument("--serve-events", type=int, default=2000,
                     help="events per arrival-rate point of the serving sweep")
     ap.add_argument("--tuning", default=None,
-                    help="chunk_digis,tile_waves,tiles_per_cu,fed_major,use_graph")
-    ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--graph", action="store_true",
-                    help="replay the batched launch as a graph (kernel time is then not measured)")
+                    help="chunk_digis,tile_waves,tiles_per_cu,fed_major instead of the autotuner")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB 5 times (reference "
@@ -100,6 +347,21 @@ def main():
               "across GPUs with host-side dispatch and no device exchange, so per-GPU throughput "
               "is the single-GPU figure.", file=sys.stderr)
         sys.exit(2)
+
+    # ---- workload: 64 full-detector events, occupancy log-uniform in [0.5%, 5%] -------------
+    cfg = fedgen.CONFIGS[2]
+    t0 = time.time()
+    cal = fedgen.make_calibration(cfg)
+    events = fedgen.make_events(cfg, cal, range(args.batch), workers=args.workers)
+    n_fed = cfg.n_fed
+    log(f"generated {len(events)} events in {time.time() - t0:.1f}s; "
+        f"ZS {sum(e.zs.size for e in events) / 1e6:.1f} MB")
+
+    # ---- CPU baseline first, before anything touches the GPU (its processes are forked) -----
+    cpu = None
+    if not args.no_cpu_baseline and not args.copy_probe_mib:
+        cpu = cpu_baseline(events, cal, n_fed, args.cpu_seconds, args.cpu_procs)
+        log(f"cpu baseline: {cpu}")
 
     import torch
     import paper_2101_11489_amd as sc
@@ -115,36 +377,27 @@ def main():
         print(json.dumps({"copy_probe_bytes": a.numel(), "copies": 5}))
         return
 
-    # ---- workload: 64 full-detector events, occupancy log-uniform in [0.5%, 5%] -------------
-    cfg = fedgen.CONFIGS[2]
-    t0 = time.time()
-    cal = fedgen.make_calibration(cfg)
-    events = fedgen.make_events(cfg, cal, range(args.batch), workers=args.workers)
-    log(f"generated {len(events)} events in {time.time() - t0:.1f}s; "
-        f"ZS {sum(e.zs.size for e in events) / 1e6:.1f} MB")
-
     stream = torch.cuda.Stream()
     ctx = sc.Context(cal.noise, cal.gain, cal.bad, device=0, stream=stream)
-    if args.tuning:
-        c, w, t, f, g = (int(x) for x in args.tuning.split(","))
-        ctx.tuning = {"chunk_digis": c, "tile_waves": w, "tiles_per_cu": t, "fed_major": f,
-                      "use_graph": g}
     devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in events]
     outs = [ctx.output(*sc.safe_caps(d)) for d in devs]
     torch.cuda.synchronize()
-    if args.autotune:
-        t = ctx.autotune(devs)
-        log(f"autotuned: {t}")
-    # The timed launches run eagerly: the library then records its HIP events on the launch
-    # stream right around the fused kernel, which gives the kernel's own duration per launch.
-    # (A captured graph is replayed as a whole; its launch overhead is negligible at this size.)
-    if not args.graph:
-        ctx.tuning = {"use_graph": 0}
+    if args.tuning:
+        c, w, t, f = (int(x) for x in args.tuning.split(",")[:4])
+        ctx.tuning = {"chunk_digis": c, "tile_waves": w, "tiles_per_cu": t, "fed_major": f}
+        tuned_by = "given"
+    else:
+        t_at = time.time()
+        ctx.autotune(devs)
+        tuned_by = f"autotuner on the batch ({time.time() - t_at:.1f} s)"
+    log(f"tuning: {ctx.tuning} ({tuned_by})")
 
     # ---- warm-up, then a sampled parity check at full size ---------------------------------
     batch = ctx.batch(devs, outs)   # argument arrays marshalled once
-    for _ in range(args.warmup):
+    ctx.tuning = {"use_graph": 1}
+    for _ in range(3):
         ctx.process_batch(batch)
+    torch.cuda.synchronize()
     parity = "skipped"
     try:
         import oracle
@@ -155,95 +408,62 @@ def main():
             cl, adc, _ = outs[i].to_numpy()
             ok &= np.array_equal(cl, ref.cl) and np.array_equal(adc, ref.adc)
         parity = "bit-exact (2 sampled events)" if ok else "MISMATCH"
-    except Exception as ex:  # the oracle is optional at bench time
+    except ImportError as ex:  # the oracle is optional at bench time
         parity = f"skipped ({ex})"
     log(f"parity: {parity}")
 
-    # ---- timed region ------------------------------------------------------------------------
-    # The calls are issued from the library's stream (nothing to order against another stream);
-    # the kernel's own durations are summed by the library and read once afterwards.
-    step_ms = []
-    torch.cuda.synchronize()
-    st0 = ctx.stats()
-    with torch.cuda.stream(stream):
-        t_start = time.perf_counter()
-        for _ in range(args.steps):
-            ts = time.perf_counter()
-            ctx.process_batch(batch)             # synchronous: returns when results are in HBM
-            step_ms.append((time.perf_counter() - ts) * 1e3)
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t_start
-    st1 = ctx.stats()
-    n_timed = st1["kernels_timed"] - st0["kernels_timed"]
-    kern_ms = ([(st1["kernel_ms_total"] - st0["kernel_ms_total"]) / n_timed] if n_timed == args.steps
-               else [])
-
-    n_fed = cfg.n_fed
+    # ---- timed region: graph replay (the stated form), then eager, then cache-cold ----------
+    g = time_steps(ctx, batch, args.steps, args.warmup, stream, torch, graph=True)
+    e = time_steps(ctx, batch, args.steps, args.warmup, stream, torch, graph=False)
     counts = [(o.n_cl, o.n_adc) for o in outs]
     n_ev = len(events)
-    ev_per_s = n_ev * args.steps / elapsed
-    ms_per_step = elapsed / args.steps * 1e3
-    kern_valid = [k for k in kern_ms if k > 0]
-    kern_avg = statistics.mean(kern_valid) if kern_valid else float("nan")
     b_alg = algorithmic_bytes(events, counts, n_fed)
-    achieved = b_alg / (kern_avg * 1e-3) / 1e9 if kern_valid else None
+    ev_per_s = n_ev * args.steps / g["elapsed_s"]
+    ms_per_step = g["elapsed_s"] / args.steps * 1e3
+    # The kernel's duration: the library's HIP events right around the eager launch of the
+    # same kernel on the same stream (inside a replayed graph the event nodes bracket more than
+    # the kernel: graph_event_bracket_ms below).
+    kern = e["kernel_ms"] if e["kernel_ms"] else g["kernel_ms"]
+    achieved = b_alg / (kern * 1e-3) / 1e9 if kern else None
     tuning = ctx.tuning
-    log(f"batched: {ev_per_s:.0f} events/s, {ms_per_step:.3f} ms/step, kernel {kern_avg:.3f} ms, "
-        f"B_alg {b_alg / 1e6:.1f} MB/launch -> {achieved} GB/s; tuning {tuning}")
+    tuning["use_graph"] = 1
+    eager = {"graph_event_bracket_ms": g["kernel_ms"],
+             "events_per_s": n_ev * args.steps / e["elapsed_s"],
+             "ms_per_step": e["elapsed_s"] / args.steps * 1e3, "kernel_ms": e["kernel_ms"],
+             "latency_ms_p50": float(np.percentile(e["step_ms"], 50)),
+             "latency_ms_p99": float(np.percentile(e["step_ms"], 99))}
+    log(f"graph: {ev_per_s:.0f} events/s, {ms_per_step:.3f} ms/step, kernel {kern} ms; "
+        f"eager: {eager}")
+    cold = None
+    if not args.no_cold:
+        flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        c = time_steps(ctx, batch, 20, 2, stream, torch, graph=False, flush=flush)
+        del flush
+        torch.cuda.empty_cache()
+        cold = {"what": "eager launches, each after a 512 MiB write on the launch stream (L2 and "
+                        "Infinity Cache emptied of the batch's inputs and calibration)",
+                "kernel_ms": c["kernel_ms"],
+                "hbm_frac": (b_alg / (c["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+                            if c["kernel_ms"] else None}
+        log(f"cold: {cold}")
+    probe = stream_probe(torch)
+    log(f"stream probe: {probe}")
 
-    # ---- the plain per-event path (sc_unpack + sc_cluster), full detector at 1.5% -----------
-    plain = None
+    # ---- plain per-event path: 50-FED and full-detector single events -----------------------
+    plain = {}
     if not args.no_plain:
-        cfg1 = fedgen.CONFIGS[1]
-        cal1 = fedgen.make_calibration(cfg1)
-        ev1 = fedgen.make_events(cfg1, cal1, range(args.plain_events), workers=args.workers)
-        ctx1 = sc.Context(cal1.noise, cal1.gain, cal1.bad, device=0, stream=stream)
-        d1 = [sc.Event(e.zs, e.fed_offset).to_device() for e in ev1]
-        o1 = [ctx1.output(*sc.safe_caps(d)) for d in d1]
-        dense = ctx1.dense_buffer()
-        for d, o in zip(d1[:2], o1[:2]):      # warm-up of both paths (and the one-event graph)
-            ctx1.unpack(d, dense)
-            ctx1.cluster(dense, o)
-            ctx1.process_events([d], [o])
-        torch.cuda.synchronize()
-        with torch.cuda.stream(stream):       # issue from the library's stream
-            tp = time.perf_counter()
-            pk = []
-            for d, o in zip(d1, o1):
-                ctx1.unpack(d, dense)
-                ku = ctx1.stats()["last_kernel_ms"]
-                ctx1.cluster(dense, o)
-                pk.append(ku + ctx1.stats()["last_kernel_ms"])
-            torch.cuda.synchronize()
-            plain_s = time.perf_counter() - tp
-            # the fused kernel, one event per launch
-            tf = time.perf_counter()
-            fk = []
-            for d, o in zip(d1, o1):
-                ctx1.process_events([d], [o])
-                fk.append(ctx1.stats()["last_kernel_ms"])
-            torch.cuda.synchronize()
-            single_s = time.perf_counter() - tf
-            # the same events as one batch
-            ctx1.process_events(d1, o1)
-            tb = time.perf_counter()
-            for _ in range(5):
-                ctx1.process_events(d1, o1)
-            torch.cuda.synchronize()
-            batch1_s = (time.perf_counter() - tb) / 5
-        b1 = algorithmic_bytes(ev1, [(o.n_cl, o.n_adc) for o in o1], cfg1.n_fed)
-        plain = {
-            "workload": f"{len(ev1)} full-detector events at 1.5% occupancy, one per call",
-            "plain_unpack_then_cluster_events_per_s": len(ev1) / plain_s,
-            "plain_kernel_ms_per_event": statistics.mean(pk),
-            "fused_one_event_per_launch_events_per_s": len(ev1) / single_s,
-            "fused_one_event_kernel_ms": statistics.mean(fk),
-            f"fused_batch_of_{len(ev1)}_events_per_s": len(ev1) / batch1_s,
-            "hbm_frac_fused_one_event": (b1 / len(ev1)) / (statistics.mean(fk) * 1e-3) / 1e9
-                                         / HBM_PEAK_GBS,
-        }
-        log(f"plain: {plain}")
-        ctx1.close()
+        for cid in (0, 1):
+            plain[f"config{cid}"] = plain_line(sc, torch, stream, cid, args.plain_events,
+                                               args.workers, tuning)
+            log(f"plain config {cid}: {plain[f'config{cid}']}")
+
+    # ---- the 256-event stress batch ------------------------------------------------------------
+    stress = None
+    if not args.no_stress:
+        cap_cl = max(c for c, _ in counts)
+        cap_adc = max(a for _, a in counts)
+        stress = stress_line(sc, torch, stream, args.workers, tuning, cap_cl, cap_adc, 5)
+        log(f"stress: {stress}")
 
     # ---- serving: Poisson arrivals of the occupancy mix {0.5,1.5,3,6}% -----------------------
     serving = None
@@ -253,8 +473,10 @@ def main():
         pool = fedgen.make_events(cfg3, cal3, range(64), workers=args.workers)
         ctx3 = sc.Context(cal3.noise, cal3.gain, cal3.bad, device=0, stream=stream,
                           max_batch=64, n_streams=2)
-        ctx3.tuning = ctx.tuning
-        p_dev = [sc.Event(e.zs, e.fed_offset).to_device() for e in pool]
+        ctx3.tuning = {k: tuning[k] for k in ("chunk_digis", "tile_waves", "tiles_per_cu",
+                                              "fed_major")}
+        ctx3.tuning = {"use_graph": 0}
+        p_dev = [sc.Event(x.zs, x.fed_offset).to_device() for x in pool]
         n_out = 256
         p_out = [ctx3.output(*sc.safe_caps(p_dev[j % len(p_dev)])) for j in range(n_out)]
         # batched capacity on this mix
@@ -282,30 +504,6 @@ def main():
                    "server_batches": ctx3.stats()["server_batches"]}
         ctx3.close()
 
-    # ---- CPU baseline: the oracle on a bounded sample, one host core ------------------------
-    # The batch events are run through the oracle in turn (cycling) until at least
-    # --cpu-seconds of CPU work is done, capped at --cpu-sample passes over the batch.
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        scratch = np.empty(n_fed * 96 * 256, np.uint8)
-        cl = np.empty(4_000_000, dtype=oracle.CLUSTER_DTYPE)
-        adc = np.empty(8_000_000, dtype=np.uint16)
-        done = 0
-        tc = time.perf_counter()
-        while True:
-            e = events[done % len(events)]
-            oracle.process_event_raw(e.zs, e.fed_offset, cal.noise, cal.gain, cal.bad, scratch,
-                                     cl, adc)
-            done += 1
-            cpu_s = time.perf_counter() - tc
-            if cpu_s >= args.cpu_seconds or done >= args.cpu_sample * len(events):
-                break
-        cpu = {"value": done / cpu_s, "unit": "events/s", "cores": 1, "kind": "oracle",
-               "sample": f"{done} events of the batch (in batch order, cycling), single-threaded "
-                         f"C oracle on one host core, {cpu_s:.1f} s"}
-        log(f"cpu baseline: {cpu}")
-
     traffic = load_traffic(f"config2-batch{n_ev}")
     line = {
         "metric": "events/s, unpack + three-threshold clustering, batched full-detector events",
@@ -322,17 +520,18 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"batched: {n_ev} full-detector events per fused persistent launch "
-                        "(440 FEDs x 96 ch x 256 strips, occupancy log-uniform 0.5-5%)",
+                        "(440 FEDs x 96 ch x 256 strips, occupancy log-uniform 0.5-5%), "
+                        "hipGraph replay, autotuned tiles",
             "n_fed": n_fed, "events_per_launch": n_ev,
-            "zs_mb_per_launch": round(sum(e.zs.size for e in events) / 1e6, 2),
+            "zs_mb_per_launch": round(sum(x.zs.size for x in events) / 1e6, 2),
             "clusters_per_launch": int(sum(c for c, _ in counts)),
-            "tuning": tuning, "device": dev_name,
+            "tuning": tuning, "tuned_by": tuned_by, "device": dev_name,
         },
         "strips_per_s": ev_per_s * n_fed * 96 * 256,
-        "digis_per_s": sum(e.n_digis for e in events) * args.steps / elapsed,
-        "latency_ms_p50": float(np.percentile(step_ms, 50)),
-        "latency_ms_p99": float(np.percentile(step_ms, 99)),
-        "kernel_ms": kern_avg,
+        "digis_per_s": sum(x.n_digis for x in events) * args.steps / g["elapsed_s"],
+        "latency_ms_p50": float(np.percentile(g["step_ms"], 50)),
+        "latency_ms_p99": float(np.percentile(g["step_ms"], 99)),
+        "kernel_ms": kern,
         "parity": parity,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -340,8 +539,13 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes_per_launch": b_alg,
             "kernel": "fused_kernel",
+            "measured_read_stream_gbs": probe["read_stream_gbs"],
+            "measured_copy_gbs": probe["copy_gbs"],
         },
-        "plain_path": plain,
+        "eager": eager,
+        "cache_cold": cold,
+        "plain_path": plain or None,
+        "stress": stress,
         "serving": serving,
         "cpu_baseline": cpu,
     }

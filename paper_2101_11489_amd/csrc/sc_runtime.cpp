@@ -1204,15 +1204,28 @@ sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best
                              nullptr, SC_MEM_DEVICE};
     }
     const sc_tuning saved = c->tuning;
+    // Stage 1: every tile shape and tile order with as many resident tiles as fit; stage 2: the
+    // best of those with fewer resident tiles per compute unit (fewer tiles in flight can shorten
+    // the look-back waits of the FEDs that follow).
     std::vector<sc_tuning> cands;
     for (uint32_t w : {1u, 2u, 4u})
         for (uint32_t d : {1024u, 2048u, 2880u, 3072u, 4096u})
             for (uint32_t fm : {0u, 1u})
                 if (tile_shape_supported(w, d)) cands.push_back(sc_tuning{d, w, 32, fm, 0});
+    const size_t n_stage1 = cands.size();
     std::vector<uint8_t> ref_cl, ref_adc, cur_cl, cur_adc;
     double best_ms = 1e30;
     sc_tuning best_t = saved;
     for (size_t ci = 0; ci < cands.size(); ++ci) {
+        if (ci == n_stage1) {
+            const int occ = fused_blocks_per_cu(best_t.tile_waves, best_t.chunk_digis, false);
+            for (int tpc = occ - 1; tpc >= std::max(1, occ - 3); --tpc) {
+                sc_tuning t = best_t;
+                t.tiles_per_cu = (uint32_t)tpc;
+                cands.push_back(t);
+            }
+            if (ci == cands.size()) break;
+        }
         c->tuning = cands[ci];
         std::vector<float> times;
         for (int rep = 0; rep < 4; ++rep) {
@@ -1227,11 +1240,15 @@ sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best
         }
         std::sort(times.begin(), times.end());
         const double ms = times[times.size() / 2];
-        // identical results for every choice
+        // identical results for every choice (the produced part of each event's outputs)
         cur_cl.resize(tot_cl);
         cur_adc.resize(tot_adc);
-        SC_HIP(c, hipMemcpy(cur_cl.data(), bcl.p, tot_cl, hipMemcpyDeviceToHost));
-        SC_HIP(c, hipMemcpy(cur_adc.data(), badc.p, tot_adc, hipMemcpyDeviceToHost));
+        for (uint32_t i = 0; i < n; ++i) {
+            const size_t ncl = std::min(out[i].n_cl, cap[i]) * sizeof(sc_cluster_rec);
+            const size_t nad = std::min(out[i].n_adc, cap[i]) * 2;
+            if (ncl) SC_HIP(c, hipMemcpy(cur_cl.data() + off_cl[i], bcl.as<uint8_t>() + off_cl[i], ncl, hipMemcpyDeviceToHost));
+            if (nad) SC_HIP(c, hipMemcpy(cur_adc.data() + off_adc[i], badc.as<uint8_t>() + off_adc[i], nad, hipMemcpyDeviceToHost));
+        }
         if (ci == 0) {
             ref_cl = cur_cl;
             ref_adc = cur_adc;
