@@ -488,20 +488,35 @@ def main():
             ctx3.process_events(p_dev, p_out[:len(p_dev)])
         torch.cuda.synchronize()
         capacity = 10 * len(p_dev) / (time.perf_counter() - tcap)
+        # a short replay first: the server's start-up and first batches are not a point's tail
+        ctx3.serve_replay(p_dev, p_out, 200, 0.5 * capacity, seed=1)
         points = []
         for frac in (0.2, 0.4, 0.6, 0.8, 1.0, 1.2):
-            rc, lat, eps = ctx3.serve_replay(p_dev, p_out, args.serve_events, frac * capacity,
-                                             seed=int(frac * 1000))
+            rc, lat, eps, ph = ctx3.serve_replay(p_dev, p_out, args.serve_events,
+                                                 frac * capacity, seed=int(frac * 1000),
+                                                 phases=True)
+            # where the time goes: the phases' medians over all events and their means over the
+            # slowest 1 %; "other" is the launch reaching the device and completion being seen
+            other = lat - ph.sum(axis=1)
+            tail = lat >= np.percentile(lat, 99)
+            names = ("output_slot_wait", "queue_wait", "device", "other")
+            cols = [ph[:, 0], ph[:, 1], ph[:, 2], other]
             points.append({"rate_frac": frac, "offered_events_per_s": frac * capacity,
                            "achieved_events_per_s": eps,
                            "latency_us_p50": float(np.percentile(lat, 50)),
-                           "latency_us_p99": float(np.percentile(lat, 99)), "status": rc})
+                           "latency_us_p99": float(np.percentile(lat, 99)), "status": rc,
+                           "phase_us_p50": {k: round(float(np.median(v)), 1)
+                                            for k, v in zip(names, cols)},
+                           "phase_us_tail_mean": {k: round(float(v[tail].mean()), 1)
+                                                  for k, v in zip(names, cols)}})
             log(f"serve {frac:.1f}: {points[-1]}")
         serving = {"workload": f"Poisson arrivals, {args.serve_events} events per point, pool of "
                                f"{len(pool)} full-detector events of the occupancy mix, device-"
                                "resident inputs and outputs",
                    "batched_capacity_events_per_s": capacity, "points": points,
-                   "server_batches": ctx3.stats()["server_batches"]}
+                   "server_batches": ctx3.stats()["server_batches"],
+                   "server_budget_bytes": ctx3.stats()["server_budget"],
+                   "server_held_peak_bytes": ctx3.stats()["server_held_peak"]}
         ctx3.close()
 
     traffic = load_traffic(f"config2-batch{n_ev}")

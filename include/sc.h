@@ -68,7 +68,8 @@ typedef enum {
     SC_PENDING = 2,            /* sc_poll: not finished yet */
     SC_ERR_INVALID_ARG = -1,   /* bad argument; nothing was done */
     SC_ERR_OVERFLOW = -2,      /* an output capacity was too small; n_cl/n_adc hold the needs */
-    SC_ERR_BUDGET = -3,        /* sc_submit: the event can never fit the HBM budget */
+    SC_ERR_BUDGET = -3,        /* sc_submit: the event can never fit the HBM budget, or the
+                                  budget is below the server's per-batch tables */
     SC_ERR_AGAIN = -4,         /* sc_submit: admission queue full, try again later */
     SC_ERR_DEVICE = -5,        /* HIP runtime or kernel failure; the context is unusable */
     SC_ERR_NOMEM = -6,         /* device or pinned allocation failed */
@@ -97,7 +98,9 @@ typedef struct {
 typedef struct {
     int device;            /* HIP device ordinal */
     void *stream;          /* hipStream_t of the synchronous calls; NULL: a stream of the context */
-    size_t hbm_budget;     /* bytes the server may hold for events in flight; 0: 1/4 of free HBM */
+    size_t hbm_budget;     /* device bytes the server may hold: its per-batch tables (sized for
+                              max_batch at start) and the staging of host events and host outputs
+                              in flight; 0: 1/4 of free HBM */
     uint32_t max_batch;    /* most events per fused launch in the server (default 64) */
     uint32_t n_streams;    /* server streams, i.e. batches in flight (default 2) */
     uint32_t queue_depth;  /* server admission queue (default 4096) */
@@ -154,6 +157,10 @@ typedef struct {
     uint64_t kernels_timed;  /* number of launches summed in kernel_ms_total */
     uint64_t allocations;    /* device and pinned-host allocations the library has made, in this
                                 process (all contexts) */
+    uint64_t server_budget;    /* the server's HBM budget in bytes (hbm_budget, or what 0
+                                  resolved to when the server started) */
+    uint64_t server_held_peak; /* most device bytes the server's workspaces held at once
+                                  (never above server_budget) */
 } sc_stats;
 
 /* Limits of sc_process_events_static. */
@@ -211,8 +218,11 @@ sc_status sc_process_events_static(sc_ctx *ctx, const sc_event *ev, uint32_t n, 
  * and returns a ticket. Host ZS bytes are copied before the call returns; device ZS
  * buffers and every output buffer must stay valid until sc_poll returns a final status. Events
  * that arrive while others run join the next batch as soon as a stream slot and HBM budget are
- * free (continuous batching). Returns SC_OK, SC_ERR_AGAIN (queue full), SC_ERR_BUDGET (can never
- * fit) or SC_ERR_INVALID_ARG. */
+ * free (continuous batching). The server thread holds one host core while batches are in flight
+ * (it polls their completion without sleeping) and sleeps when idle. What the server allocates
+ * (per-batch tables for max_batch events on each stream slot, from the start, and staging for
+ * host events and host outputs) stays within hbm_budget. Returns SC_OK, SC_ERR_AGAIN (queue
+ * full), SC_ERR_BUDGET (can never fit) or SC_ERR_INVALID_ARG. */
 sc_status sc_submit(sc_ctx *ctx, const sc_event *ev, sc_clusters *out, uint64_t *ticket);
 
 /* Completion side of the serving loop (§3: events processed concurrently, each collected when
@@ -225,11 +235,15 @@ sc_status sc_poll(sc_ctx *ctx, uint64_t ticket, int64_t timeout_us);
  * rate_hz (exponential gaps from a generator seeded with seed), event i using ev[i % n_ev] and
  * out[i % n_out]; an output slot is reused only once its previous event has completed. On return
  * every event has completed; latency_us[i] (optional, n entries) receives completion time minus
- * scheduled arrival time in microseconds (queueing included), *events_per_s (optional) the
+ * scheduled arrival time in microseconds (queueing included). phase_us (optional, 3n entries)
+ * splits it: [3i] arrival to submit (the previous event on its output slot not yet done),
+ * [3i+1] submit to launch (waiting for a stream slot or for budget), [3i+2] its batch on the
+ * device (copies in, kernels, results back); the rest of latency_us[i] is the launch reaching the
+ * device and the completion being noticed and finished. *events_per_s (optional) receives the
  * completed events per second over the run. Returns the worst event status. */
 sc_status sc_serve_replay(sc_ctx *ctx, const sc_event *ev, uint32_t n_ev, sc_clusters *out,
                           uint32_t n_out, uint32_t n, double rate_hz, uint64_t seed,
-                          double *latency_us, double *events_per_s);
+                          double *latency_us, double *phase_us, double *events_per_s);
 
 /* Tuning of the fused kernel. sc_autotune times every candidate choice on the given events
  * (device or host), checks that all choices give identical clusters, keeps the fastest and, if

@@ -81,7 +81,8 @@ class ScStats(ctypes.Structure):
                 ("server_batches", ctypes.c_uint64), ("server_events", ctypes.c_uint64),
                 ("server_rejected_again", ctypes.c_uint64), ("last_kernel_ms", ctypes.c_double),
                 ("kernel_ms_total", ctypes.c_double), ("kernels_timed", ctypes.c_uint64),
-                ("allocations", ctypes.c_uint64)]
+                ("allocations", ctypes.c_uint64), ("server_budget", ctypes.c_uint64),
+                ("server_held_peak", ctypes.c_uint64)]
 
 
 _lib = None
@@ -112,7 +113,7 @@ def lib():
             "sc_poll": ([P, ctypes.c_uint64, ctypes.c_int64], st),
             "sc_serve_replay": ([P, ctypes.POINTER(ScEvent), ctypes.c_uint32,
                                  ctypes.POINTER(ScClusters), ctypes.c_uint32, ctypes.c_uint32,
-                                 ctypes.c_double, ctypes.c_uint64,
+                                 ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
                                 st),
             "sc_get_tuning": ([P, ctypes.POINTER(ScTuning)], st),
@@ -398,19 +399,25 @@ class Context:
             self._pending.pop(ticket, None)
         return rc
 
-    def serve_replay(self, events, outs, n, rate_hz, seed=11489):
-        """Open-loop Poisson load on the server. Returns (status, latencies_us[n], events/s)."""
+    def serve_replay(self, events, outs, n, rate_hz, seed=11489, phases=False):
+        """Open-loop Poisson load on the server. Returns (status, latencies_us[n], events/s), and
+        with phases=True also an [n, 3] array: arrival to submit, submit to launch, device time
+        of the event's batch (microseconds)."""
         self._ready_for_server()
         evs = (ScEvent * len(events))(*[e.c() for e in events])
         cs = (ScClusters * len(outs))(*[o.cs for o in outs])
         lat = (ctypes.c_double * n)()
+        ph = (ctypes.c_double * (3 * n))() if phases else None
         eps = ctypes.c_double()
         rc = lib().sc_serve_replay(self._h, evs, len(events), cs, len(outs), n, rate_hz, seed,
-                                   lat, ctypes.byref(eps))
+                                   lat, ph, ctypes.byref(eps))
         for o, c in zip(outs, cs):
             o.cs.n_cl, o.cs.n_adc = c.n_cl, c.n_adc
         self._check(rc, (SC_OK, SC_MALFORMED, SC_ERR_OVERFLOW))
-        return rc, np.frombuffer(lat, dtype=np.float64).copy(), eps.value
+        lat = np.frombuffer(lat, dtype=np.float64).copy()
+        if phases:
+            return rc, lat, eps.value, np.frombuffer(ph, dtype=np.float64).reshape(n, 3).copy()
+        return rc, lat, eps.value
 
     # -- tuning / stats --
     @property

@@ -113,7 +113,21 @@ struct Workspace {
         for (DevBuf* b : {&desc, &res, &state, &queue, &zs, &fo, &cl, &adc, &chst, &dense}) b->release();
         for (PinBuf* b : {&h_desc, &h_res, &h_zs, &h_fo}) b->release();
     }
+    // host-event and host-output staging (grown per batch), not the per-batch tables
+    void release_staging() {
+        for (DevBuf* b : {&zs, &fo, &cl, &adc, &chst}) b->release();
+        for (PinBuf* b : {&h_zs, &h_fo}) b->release();
+    }
+    size_t device_bytes() const {
+        size_t t = 0;
+        for (const DevBuf* b : {&desc, &res, &state, &queue, &zs, &fo, &cl, &adc, &chst, &dense})
+            t += b->n;
+        return t;
+    }
 };
+
+// What DevBuf::ensure allocates for a request of `bytes` (0: nothing).
+size_t devbuf_size(size_t bytes) { return bytes ? align_up(std::max<size_t>(bytes, 256), 4096) : 0; }
 
 struct GraphKey {
     uint32_t n_ev, chunk, waves, grid, fed_major;
@@ -553,7 +567,8 @@ struct Req {
     std::vector<uint64_t> fo_copy;
     size_t bytes = 0;                     // budget reservation
     sc_status status = SC_PENDING;
-    std::chrono::steady_clock::time_point t_submit, t_done;
+    std::chrono::steady_clock::time_point t_submit, t_launch, t_done;
+    float device_ms = 0;                  // its batch on the device: first copy to the results back
 };
 }  // namespace
 
@@ -566,11 +581,13 @@ struct Server {
     std::unordered_map<uint64_t, std::shared_ptr<Req>> tickets;
     uint64_t next_id = 1;
     size_t budget = 0, reserved = 0;
+    size_t held_peak = 0;   // most device bytes the slots' workspaces held at once
+    size_t held_fixed = 0;  // the slots' per-batch tables (held from the start)
     bool stop = false;
     struct Slot {
         hipStream_t s = nullptr;
         Workspace ws;
-        hipEvent_t done = nullptr;
+        hipEvent_t t0 = nullptr, done = nullptr;
         std::vector<std::shared_ptr<Req>> batch;
         Staged st;
         bool busy = false;
@@ -588,9 +605,18 @@ struct Server {
         slots.resize(ns);
         for (auto& sl : slots) {
             if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+                hipEventCreate(&sl.t0) != hipSuccess || hipEventCreate(&sl.done) != hipSuccess)
                 return SC_ERR_DEVICE;
+            // the per-batch tables for the largest batch, once: a batch of device events never
+            // allocates (and never frees, which would wait for the other slots' kernels)
+            if (sl.ws.ensure_batch(std::max<uint32_t>(1, c->opt.max_batch), c->n_fed) != hipSuccess)
+                return SC_ERR_NOMEM;
         }
+        held_fixed = held();
+        if (held_fixed > budget) return SC_ERR_BUDGET;
+        held_peak = held_fixed;
+        c->stats.server_budget = budget;
+        c->stats.server_held_peak = held_peak;
         thr = std::thread([this] { loop(); });
         return SC_OK;
     }
@@ -606,22 +632,61 @@ struct Server {
             if (sl.s) (void)hipStreamSynchronize(sl.s);
             sl.ws.release();
             if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.t0) (void)hipEventDestroy(sl.t0);
             if (sl.s) (void)hipStreamDestroy(sl.s);
         }
     }
 
+    size_t held() const {
+        size_t t = 0;
+        for (const auto& sl : slots) t += sl.ws.device_bytes();
+        return t;
+    }
+
+    // Device bytes the server needs for one request beyond the per-batch tables: staging of a host
+    // event and of host outputs (device events and outputs are the caller's).
     static size_t reservation(const sc_ctx* c, const sc_event& ev, const sc_clusters& o) {
         size_t b = sizeof(unsigned long long) * c->n_fed + sizeof(EventDesc) + sizeof(EventResult);
-        b += sizeof(sc_cluster_rec) * (size_t)o.cap_cl + sizeof(uint16_t) * (size_t)o.cap_adc;
-        if (o.chan_status) b += (size_t)c->n_fed * kChannelsPerFed;
-        if (ev.mem == SC_MEM_HOST) b += event_span(ev.fed_offset, c->n_fed);
+        // rounded as the staging buffers are, so that one request alone always fits its slot
+        if (o.mem == SC_MEM_HOST) {
+            b += devbuf_size(align_up(sizeof(sc_cluster_rec) * (size_t)o.cap_cl, 256)) +
+                 devbuf_size(align_up(sizeof(uint16_t) * (size_t)o.cap_adc, 256));
+            if (o.chan_status) b += devbuf_size(align_up((size_t)c->n_fed * kChannelsPerFed, 256));
+        }
+        if (ev.mem == SC_MEM_HOST)
+            b += devbuf_size(align_up(event_span(ev.fed_offset, c->n_fed), 16)) +
+                 devbuf_size(align_up(sizeof(uint64_t) * (c->n_fed + 1), 16));
         return b;
+    }
+
+    // Device bytes slot `sl` would hold after staging this batch (its buffers only grow).
+    size_t slot_bytes_after(const Slot& sl, const std::vector<sc_event>& evs,
+                            const std::vector<sc_clusters>& outs) const {
+        size_t zs = 0, fo = 0, cl = 0, adc = 0, st = 0;
+        for (size_t i = 0; i < evs.size(); ++i) {
+            if (evs[i].mem == SC_MEM_HOST) {
+                zs += align_up(event_span(evs[i].fed_offset, c->n_fed), 16);
+                fo += align_up(sizeof(uint64_t) * (c->n_fed + 1), 16);
+            }
+            if (outs[i].mem == SC_MEM_HOST) {
+                cl += align_up(sizeof(sc_cluster_rec) * (uint64_t)outs[i].cap_cl, 256);
+                adc += align_up(sizeof(uint16_t) * (uint64_t)outs[i].cap_adc, 256);
+                if (outs[i].chan_status) st += align_up((uint64_t)c->n_fed * kChannelsPerFed, 256);
+            }
+        }
+        const Workspace& w = sl.ws;
+        size_t t = w.desc.n + w.res.n + w.state.n + w.queue.n + w.dense.n;
+        t += std::max(w.zs.n, devbuf_size(zs)) + std::max(w.fo.n, devbuf_size(fo));
+        t += std::max(w.cl.n, devbuf_size(cl)) + std::max(w.adc.n, devbuf_size(adc));
+        t += std::max(w.chst.n, devbuf_size(st));
+        return t;
     }
 
     sc_status submit(const sc_event& ev, sc_clusters* out, uint64_t* ticket) {
         auto r = std::make_shared<Req>();
         r->bytes = reservation(c, ev, *out);
-        if (r->bytes > budget) return fail(c, SC_ERR_BUDGET, "event larger than the HBM budget");
+        if (r->bytes + held_fixed > budget)
+            return fail(c, SC_ERR_BUDGET, "event larger than the HBM budget");
         r->ev = ev;
         r->out = out;
         if (ev.mem == SC_MEM_HOST) {
@@ -648,7 +713,9 @@ struct Server {
     }
 
     sc_status poll(uint64_t ticket, int64_t timeout_us,
-                   std::chrono::steady_clock::time_point* t_done = nullptr) {
+                   std::chrono::steady_clock::time_point* t_done = nullptr,
+                   std::chrono::steady_clock::time_point* t_launch = nullptr,
+                   float* device_ms = nullptr) {
         std::unique_lock<std::mutex> g(mu);
         auto it = tickets.find(ticket);
         if (it == tickets.end()) return SC_ERR_UNKNOWN_TICKET;
@@ -662,6 +729,8 @@ struct Server {
         if (!done()) return SC_PENDING;
         tickets.erase(ticket);
         if (t_done) *t_done = r->t_done;
+        if (t_launch) *t_launch = r->t_launch;
+        if (device_ms) *device_ms = r->device_ms;
         return r->status;
     }
 
@@ -676,22 +745,51 @@ struct Server {
             std::lock_guard<std::mutex> g(mu);
             const uint32_t maxb = std::max<uint32_t>(1, c->opt.max_batch);
             while (!waiting.empty() && batch.size() < maxb &&
-                   reserved + waiting.front()->bytes <= budget) {
+                   held_fixed + reserved + waiting.front()->bytes <= budget) {
                 reserved += waiting.front()->bytes;
                 batch.push_back(waiting.front());
                 waiting.pop_front();
             }
         }
         if (batch.empty()) return false;
-        const uint32_t n = (uint32_t)batch.size();
-        std::vector<sc_event> evs(n);
-        std::vector<sc_clusters> outs(n);
-        for (uint32_t i = 0; i < n; ++i) {
+        std::vector<sc_event> evs(batch.size());
+        std::vector<sc_clusters> outs(batch.size());
+        for (size_t i = 0; i < batch.size(); ++i) {
             evs[i] = batch[i]->ev;
             outs[i] = *batch[i]->out;
         }
-        sc_status st = stage_batch(c, slot->ws, evs.data(), n, outs.data(), slot->s, slot->st);
-        hipError_t e = hipSuccess;
+        // What the slots hold stays within the budget. If this slot's staging would grow past it,
+        // the idle slots give their staging back (a device-wide free, so only then); then the
+        // batch sheds requests from its tail; a single request that still does not fit waits for
+        // a busy slot to finish (with every slot idle it fits: its reservation covers it).
+        auto fits = [&] {
+            return held() - slot->ws.device_bytes() + slot_bytes_after(*slot, evs, outs) <= budget;
+        };
+        auto give_back = [&](size_t keep) {
+            std::lock_guard<std::mutex> g(mu);
+            while (batch.size() > keep) {
+                reserved -= batch.back()->bytes;
+                waiting.push_front(batch.back());
+                batch.pop_back();
+                evs.pop_back();
+                outs.pop_back();
+            }
+        };
+        if (!fits()) {
+            for (auto& sl : slots)
+                if (!sl.busy) sl.ws.release_staging();
+            while (!fits() && batch.size() > 1) give_back(batch.size() - 1);
+            if (!fits()) {
+                give_back(0);
+                return false;
+            }
+        }
+        const uint32_t n = (uint32_t)batch.size();
+        const auto t_launch = std::chrono::steady_clock::now();
+        for (auto& r : batch) r->t_launch = t_launch;
+        hipError_t e = hipEventRecord(slot->t0, slot->s);
+        sc_status st = e == hipSuccess ? stage_batch(c, slot->ws, evs.data(), n, outs.data(), slot->s, slot->st)
+                                       : SC_ERR_DEVICE;
         if (st == SC_OK) e = enqueue_batch(c, slot->ws, n, slot->s, false);
         if (st == SC_OK && e == hipSuccess) e = hipEventRecord(slot->done, slot->s);
         if (st != SC_OK || e != hipSuccess) {
@@ -701,6 +799,8 @@ struct Server {
         }
         slot->batch = std::move(batch);
         slot->busy = true;
+        held_peak = std::max(held_peak, held());
+        c->stats.server_held_peak = held_peak;
         c->stats.server_batches++;
         c->stats.server_events += n;
         return true;
@@ -736,8 +836,13 @@ struct Server {
                 sl.busy = false;
                 continue;
             }
+            float dev_ms = 0;
+            if (hipEventElapsedTime(&dev_ms, sl.t0, sl.done) != hipSuccess) dev_ms = 0;
             std::vector<sc_clusters> outs(n);
-            for (uint32_t i = 0; i < n; ++i) outs[i] = *sl.batch[i]->out;
+            for (uint32_t i = 0; i < n; ++i) {
+                outs[i] = *sl.batch[i]->out;
+                sl.batch[i]->device_ms = dev_ms;
+            }
             std::vector<sc_status> sts(n, SC_OK);
             sc_status fs = finish_batch(c, sl.ws, sl.st, n, outs.data(), sts.data(), sl.s);
             for (uint32_t i = 0; i < n; ++i) {
@@ -760,9 +865,16 @@ struct Server {
             bool busy = false;
             for (auto& sl : slots) busy |= sl.busy;
             if (!progressed) {
-                if (busy) cv_work.wait_for(g, std::chrono::microseconds(20));
-                else cv_work.wait_for(g, std::chrono::milliseconds(5),
-                                      [&] { return stop || !waiting.empty(); });
+                // While batches are in flight the thread polls their events and the queue without
+                // sleeping (a timed wait would oversleep by the timer slack, tens of
+                // microseconds, on every completion); idle, it sleeps until a submission.
+                if (busy) {
+                    g.unlock();
+                    std::this_thread::yield();
+                } else {
+                    cv_work.wait_for(g, std::chrono::milliseconds(5),
+                                     [&] { return stop || !waiting.empty(); });
+                }
             }
         }
     }
@@ -1058,6 +1170,20 @@ sc_status sc_process_events_static(sc_ctx* c, const sc_event* ev, uint32_t n, sc
     return total;
 }
 
+// The server (streams, per-batch tables, thread) starts on first use.
+static sc_status ensure_server(sc_ctx* c) {
+    std::lock_guard<std::mutex> g(c->server_mu);
+    if (c->server) return SC_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SC_ERR_DEVICE, "hipSetDevice");
+    auto sv = std::make_unique<Server>(c);
+    const sc_status ss = sv->start();
+    if (ss == SC_ERR_BUDGET)
+        return fail(c, ss, "hbm_budget is below the server's per-batch tables");
+    if (ss != SC_OK) return fail(c, ss, "server start");
+    c->server = std::move(sv);
+    return SC_OK;
+}
+
 sc_status sc_submit(sc_ctx* c, const sc_event* ev, sc_clusters* out, uint64_t* ticket) {
     if (!c) return SC_ERR_INVALID_ARG;
     if (c->poisoned) return SC_ERR_DEVICE;
@@ -1066,15 +1192,8 @@ sc_status sc_submit(sc_ctx* c, const sc_event* ev, sc_clusters* out, uint64_t* t
     if (s != SC_OK) return s;
     s = check_out(c, *out);
     if (s != SC_OK) return s;
-    {
-        std::lock_guard<std::mutex> g(c->server_mu);
-        if (!c->server) {
-            if (hipSetDevice(c->device) != hipSuccess) return fail(c, SC_ERR_DEVICE, "hipSetDevice");
-            auto sv = std::make_unique<Server>(c);
-            if (sv->start() != SC_OK) return fail(c, SC_ERR_DEVICE, "server start");
-            c->server = std::move(sv);
-        }
-    }
+    s = ensure_server(c);
+    if (s != SC_OK) return s;
     return c->server->submit(*ev, out, ticket);
 }
 
@@ -1091,7 +1210,7 @@ sc_status sc_poll(sc_ctx* c, uint64_t ticket, int64_t timeout_us) {
 
 sc_status sc_serve_replay(sc_ctx* c, const sc_event* ev, uint32_t n_ev, sc_clusters* out,
                           uint32_t n_out, uint32_t n, double rate_hz, uint64_t seed,
-                          double* latency_us, double* events_per_s) {
+                          double* latency_us, double* phase_us, double* events_per_s) {
     using clk = std::chrono::steady_clock;
     if (!c) return SC_ERR_INVALID_ARG;
     if (!ev || !out || n_ev == 0 || n_out == 0 || !(rate_hz > 0))
@@ -1105,18 +1224,27 @@ sc_status sc_serve_replay(sc_ctx* c, const sc_event* ev, uint32_t n_ev, sc_clust
         z ^= z >> 31;
         return ((double)(z >> 11) + 1.0) * (1.0 / 9007199254740992.0);
     };
+    // started before the clock, so that its set-up does not delay the first arrivals
+    sc_status ss = ensure_server(c);
+    if (ss != SC_OK) return ss;
     std::vector<uint64_t> slot_ticket(n_out, 0);
     std::vector<int64_t> slot_event(n_out, -1);
-    std::vector<clk::time_point> t_arr(n);
+    std::vector<clk::time_point> t_arr(n), t_submit(n);
     std::vector<uint64_t> tickets(n, 0);
     sc_status worst_st = SC_OK;
     auto collect = [&](uint32_t j) -> sc_status {
         if (!slot_ticket[j]) return SC_OK;
-        clk::time_point td;
-        sc_status s = c->server->poll(slot_ticket[j], -1, &td);
+        clk::time_point td, tl;
+        float dev_ms = 0;
+        sc_status s = c->server->poll(slot_ticket[j], -1, &td, &tl, &dev_ms);
         const int64_t i = slot_event[j];
-        if (latency_us && i >= 0)
-            latency_us[i] = std::chrono::duration<double, std::micro>(td - t_arr[i]).count();
+        using us = std::chrono::duration<double, std::micro>;
+        if (latency_us && i >= 0) latency_us[i] = us(td - t_arr[i]).count();
+        if (phase_us && i >= 0) {
+            phase_us[3 * i + 0] = us(t_submit[i] - t_arr[i]).count();
+            phase_us[3 * i + 1] = us(tl - t_submit[i]).count();
+            phase_us[3 * i + 2] = 1000.0 * dev_ms;
+        }
         slot_ticket[j] = 0;
         worst_st = worst(worst_st, s);
         return s;
@@ -1132,6 +1260,7 @@ sc_status sc_serve_replay(sc_ctx* c, const sc_event* ev, uint32_t n_ev, sc_clust
         if (collect(j) == SC_ERR_DEVICE) return SC_ERR_DEVICE;
         uint64_t t = 0;
         for (;;) {
+            t_submit[i] = clk::now();
             sc_status s = sc_submit(c, &ev[i % n_ev], &out[j], &t);
             if (s == SC_OK) break;
             if (s != SC_ERR_AGAIN) return s;

@@ -252,9 +252,9 @@ def test_server_budget_and_backpressure(full):
     host = sc.Event(evs[0].zs, evs[0].fed_offset)
     cap_cl, cap_adc = refs[0].cl.size, refs[0].adc.size
     one = host.zs.size + 16 * cap_cl + 2 * cap_adc + 8 * 440 + 64
-    # budget below one event: refused outright
+    # budget below what one host event with host outputs needs staged: refused outright
     with make_ctx(cal.noise, cal.gain, cal.bad, hbm_budget=one // 2) as ctx:
-        o = ctx.output(cap_cl, cap_adc)
+        o = ctx.output(cap_cl, cap_adc, device=False)
         rc, _ = ctx.try_submit(host, o)
         assert rc == sc.SC_ERR_BUDGET
     # budget of ~1.5 events, one batch slot, queue of 1: submissions bounce with AGAIN while
@@ -277,6 +277,36 @@ def test_server_budget_and_backpressure(full):
         for t, o in accepted:
             assert ctx.poll(t, -1) == sc.SC_OK
             compare_clusters(*o.to_numpy()[:2], refs[0], "budgeted")
+
+
+def test_server_holds_within_budget_on_mixed_sizes(full):
+    """Host events and host outputs of uneven sizes in a random order, with a budget of about
+    two and a half of the largest requests: every event completes exactly, and the device bytes
+    the server held (its per-batch tables plus staging) never exceeded the budget."""
+    cal, evs, refs, _ = full
+    hosts = [sc.Event(e.zs, e.fed_offset) for e in evs]
+    caps = [sc.safe_caps(h) for h in hosts]
+    largest = max(h.zs.size + 16 * c + 2 * c2 + 8 * 441 + 64 * 1024 for h, (c, c2) in zip(hosts, caps))
+    budget = int(2.5 * largest)
+    rng = np.random.default_rng(7)
+    order = rng.permutation(np.repeat(np.arange(len(evs)), 4))
+    with make_ctx(cal.noise, cal.gain, cal.bad, hbm_budget=budget, max_batch=4, n_streams=2) as ctx:
+        served = []
+        for i in order:
+            o = ctx.output(*caps[i], device=False)
+            served.append((int(i), ctx.submit(hosts[i], o), o))
+        for i, t, o in served:
+            assert ctx.poll(t, -1) == sc.SC_OK
+            compare_clusters(*o.to_numpy()[:2], refs[i], f"budgeted event {i}")
+        st = ctx.stats()
+        assert st["server_budget"] == budget
+        assert 0 < st["server_held_peak"] <= budget
+        assert st["server_events"] == len(order)
+    # a budget below the per-batch tables is refused when the server starts
+    with make_ctx(cal.noise, cal.gain, cal.bad, hbm_budget=4096, max_batch=64) as ctx:
+        o = ctx.output(*caps[0])
+        rc, _ = ctx.try_submit(hosts[0].to_device(), o)
+        assert rc == sc.SC_ERR_BUDGET
 
 
 def test_autotune_identical_and_cached(full, tmp_path):
@@ -302,9 +332,13 @@ def test_serve_replay_poisson(full):
     with make_ctx(cal.noise, cal.gain, cal.bad, max_batch=8, n_streams=2) as ctx:
         devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs]
         outs = [ctx.output(*sc.safe_caps(devs[j % len(devs)])) for j in range(2 * len(devs))]
-        rc, lat, eps = ctx.serve_replay(devs, outs, 300, rate_hz=20000.0, seed=3)
+        rc, lat, eps, ph = ctx.serve_replay(devs, outs, 300, rate_hz=20000.0, seed=3,
+                                            phases=True)
         assert rc == sc.SC_OK
         assert lat.shape == (300,) and (lat > 0).all()
+        # the phases are non-negative and together within the latency
+        assert ph.shape == (300, 3) and (ph >= 0).all() and (ph[:, 2] > 0).all()
+        assert (ph.sum(axis=1) <= lat + 1.0).all()
         assert eps > 0
         for j, o in enumerate(outs):
             compare_clusters(*o.to_numpy()[:2], refs[j % len(devs)], f"replay slot {j}")
