@@ -65,16 +65,20 @@ def kernel_sha():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def load_traffic(n_launch_bytes_key):
+def load_traffic(workload, tuning):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on the
-    current kernel source; else None."""
+    current kernel source, this workload and this tuning; else None."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_sha() or t.get("workload") != n_launch_bytes_key:
+    if t.get("kernel_sha") != kernel_sha():
         return None
-    return t.get("hbm_bytes_per_launch")
+    key = [tuning[k] for k in ("chunk_digis", "tile_waves", "tiles_per_cu", "fed_major")]
+    for ent in t.get("entries", []):
+        if ent.get("workload") == workload and ent.get("tuning") == key:
+            return ent.get("hbm_bytes_per_launch")
+    return None
 
 
 def host_cpu():
@@ -316,6 +320,64 @@ def stress_line(sc, torch, stream, workers, tuning, cap_cl, cap_adc, steps):
     }
 
 
+def serving_sweep(sc, torch, stream, args, tuning, fracs):
+    """Open-loop Poisson arrivals through the server at fractions of the batched capacity of a
+    pool of full-detector events of the occupancy mix, device-resident inputs and outputs."""
+    cfg3 = fedgen.CONFIGS[3]
+    cal3 = fedgen.make_calibration(cfg3)
+    pool = fedgen.make_events(cfg3, cal3, range(64), workers=args.workers)
+    ctx3 = sc.Context(cal3.noise, cal3.gain, cal3.bad, device=0, stream=stream,
+                      max_batch=64, n_streams=2)
+    if tuning is not None:
+        ctx3.tuning = {k: tuning[k] for k in ("chunk_digis", "tile_waves", "tiles_per_cu",
+                                              "fed_major")}
+    ctx3.tuning = {"use_graph": 0}
+    p_dev = [sc.Event(x.zs, x.fed_offset).to_device() for x in pool]
+    n_out = 256
+    p_out = [ctx3.output(*sc.safe_caps(p_dev[j % len(p_dev)])) for j in range(n_out)]
+    # batched capacity on this mix
+    for _ in range(3):
+        ctx3.process_events(p_dev, p_out[:len(p_dev)])
+    torch.cuda.synchronize()
+    tcap = time.perf_counter()
+    for _ in range(10):
+        ctx3.process_events(p_dev, p_out[:len(p_dev)])
+    torch.cuda.synchronize()
+    capacity = 10 * len(p_dev) / (time.perf_counter() - tcap)
+    # a short replay first: the server's start-up and first batches are not a point's tail
+    ctx3.serve_replay(p_dev, p_out, 200, 0.5 * capacity, seed=1)
+    points = []
+    for frac in fracs:
+        rc, lat, eps, ph = ctx3.serve_replay(p_dev, p_out, args.serve_events,
+                                             frac * capacity, seed=int(frac * 1000),
+                                             phases=True)
+        # where the time goes: the phases' medians over all events and their means over the
+        # slowest 1 %; "other" is the launch reaching the device and completion being seen
+        other = lat - ph.sum(axis=1)
+        tail = lat >= np.percentile(lat, 99)
+        names = ("output_slot_wait", "queue_wait", "device", "other")
+        cols = [ph[:, 0], ph[:, 1], ph[:, 2], other]
+        points.append({"rate_frac": frac, "offered_events_per_s": frac * capacity,
+                       "achieved_events_per_s": eps,
+                       "latency_us_p50": float(np.percentile(lat, 50)),
+                       "latency_us_p99": float(np.percentile(lat, 99)), "status": rc,
+                       "phase_us_p50": {k: round(float(np.median(v)), 1)
+                                        for k, v in zip(names, cols)},
+                       "phase_us_tail_mean": {k: round(float(v[tail].mean()), 1)
+                                              for k, v in zip(names, cols)}})
+        log(f"serve {frac:.1f}: {points[-1]}")
+    st = ctx3.stats()
+    serving = {"workload": f"Poisson arrivals, {args.serve_events} events per point, pool of "
+                           f"{len(pool)} full-detector events of the occupancy mix, device-"
+                           "resident inputs and outputs",
+               "batched_capacity_events_per_s": capacity, "points": points,
+               "server_batches": st["server_batches"],
+               "server_budget_bytes": st["server_budget"],
+               "server_held_peak_bytes": st["server_held_peak"]}
+    ctx3.close()
+    return serving
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -337,6 +399,9 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="chunk_digis,tile_waves,tiles_per_cu,fed_major instead of the autotuner")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--serve-only", type=float, default=None, metavar="FRAC",
+                    help="only run the serving replay at this fraction of the batched capacity "
+                         "(default tuning) and print its JSON")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB 5 times (reference "
                          "for the HBM byte counters) and exit")
@@ -347,6 +412,14 @@ def main():
               "across GPUs with host-side dispatch and no device exchange, so per-GPU throughput "
               "is the single-GPU figure.", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve_only is not None:
+        import torch
+        import paper_2101_11489_amd as sc
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        print(json.dumps(serving_sweep(sc, torch, torch.cuda.Stream(), args, None,
+                                       (args.serve_only,))))
+        return
 
     # ---- workload: 64 full-detector events, occupancy log-uniform in [0.5%, 5%] -------------
     cfg = fedgen.CONFIGS[2]
@@ -468,58 +541,9 @@ def main():
     # ---- serving: Poisson arrivals of the occupancy mix {0.5,1.5,3,6}% -----------------------
     serving = None
     if not args.no_serve:
-        cfg3 = fedgen.CONFIGS[3]
-        cal3 = fedgen.make_calibration(cfg3)
-        pool = fedgen.make_events(cfg3, cal3, range(64), workers=args.workers)
-        ctx3 = sc.Context(cal3.noise, cal3.gain, cal3.bad, device=0, stream=stream,
-                          max_batch=64, n_streams=2)
-        ctx3.tuning = {k: tuning[k] for k in ("chunk_digis", "tile_waves", "tiles_per_cu",
-                                              "fed_major")}
-        ctx3.tuning = {"use_graph": 0}
-        p_dev = [sc.Event(x.zs, x.fed_offset).to_device() for x in pool]
-        n_out = 256
-        p_out = [ctx3.output(*sc.safe_caps(p_dev[j % len(p_dev)])) for j in range(n_out)]
-        # batched capacity on this mix
-        for _ in range(3):
-            ctx3.process_events(p_dev, p_out[:len(p_dev)])
-        torch.cuda.synchronize()
-        tcap = time.perf_counter()
-        for _ in range(10):
-            ctx3.process_events(p_dev, p_out[:len(p_dev)])
-        torch.cuda.synchronize()
-        capacity = 10 * len(p_dev) / (time.perf_counter() - tcap)
-        # a short replay first: the server's start-up and first batches are not a point's tail
-        ctx3.serve_replay(p_dev, p_out, 200, 0.5 * capacity, seed=1)
-        points = []
-        for frac in (0.2, 0.4, 0.6, 0.8, 1.0, 1.2):
-            rc, lat, eps, ph = ctx3.serve_replay(p_dev, p_out, args.serve_events,
-                                                 frac * capacity, seed=int(frac * 1000),
-                                                 phases=True)
-            # where the time goes: the phases' medians over all events and their means over the
-            # slowest 1 %; "other" is the launch reaching the device and completion being seen
-            other = lat - ph.sum(axis=1)
-            tail = lat >= np.percentile(lat, 99)
-            names = ("output_slot_wait", "queue_wait", "device", "other")
-            cols = [ph[:, 0], ph[:, 1], ph[:, 2], other]
-            points.append({"rate_frac": frac, "offered_events_per_s": frac * capacity,
-                           "achieved_events_per_s": eps,
-                           "latency_us_p50": float(np.percentile(lat, 50)),
-                           "latency_us_p99": float(np.percentile(lat, 99)), "status": rc,
-                           "phase_us_p50": {k: round(float(np.median(v)), 1)
-                                            for k, v in zip(names, cols)},
-                           "phase_us_tail_mean": {k: round(float(v[tail].mean()), 1)
-                                                  for k, v in zip(names, cols)}})
-            log(f"serve {frac:.1f}: {points[-1]}")
-        serving = {"workload": f"Poisson arrivals, {args.serve_events} events per point, pool of "
-                               f"{len(pool)} full-detector events of the occupancy mix, device-"
-                               "resident inputs and outputs",
-                   "batched_capacity_events_per_s": capacity, "points": points,
-                   "server_batches": ctx3.stats()["server_batches"],
-                   "server_budget_bytes": ctx3.stats()["server_budget"],
-                   "server_held_peak_bytes": ctx3.stats()["server_held_peak"]}
-        ctx3.close()
+        serving = serving_sweep(sc, torch, stream, args, tuning, (0.2, 0.4, 0.6, 0.8, 1.0, 1.2))
 
-    traffic = load_traffic(f"config2-batch{n_ev}")
+    traffic = load_traffic(f"config2-batch{n_ev}", tuning)
     line = {
         "metric": "events/s, unpack + three-threshold clustering, batched full-detector events",
         "value": ev_per_s,

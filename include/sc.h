@@ -144,7 +144,12 @@ typedef struct {
     uint32_t chunk_digis;    /* digis a tile holds in LDS per pass: 2048, 3072, 4096; 1024 with 1 wave, 2880 with 2 */
     uint32_t tile_waves;     /* wavefronts per tile: 1, 2 or 4 (each takes 96/W channels) */
     uint32_t tiles_per_cu;   /* cap on resident tiles per compute unit (persistent grid), 1..32 */
-    uint32_t fed_major;      /* 1: tiles ordered FED-major (calibration reuse), 0: event-major */
+    uint32_t fed_major;      /* tile order: 0 event-major; 1 FED-major (a FED's calibration
+                                reused from cache by its events); 2 FED-major with the FEDs dealt
+                                to one queue per XCD (reused from one L2 instead of eight). The
+                                synchronous calls run order-2 launches one at a time per process;
+                                the server's launches use order 1 in its place. Other values
+                                are taken as 1. */
     uint32_t use_graph;      /* 1: replay the batched launch as a captured hipGraph */
 } sc_tuning;
 

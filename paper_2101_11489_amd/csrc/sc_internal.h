@@ -41,14 +41,19 @@ struct DeviceCalib {
     float t_seed, t_channel, t_cluster;
 };
 
+// Tile ticket counters, one per 128-byte line: counter 0 (orders 0 and 1) or one per XCD
+// (order 2, at most 8).
+constexpr uint32_t kQueueStride = 32;
+constexpr size_t kQueueBytes = 8 * kQueueStride * sizeof(uint32_t);
+
 struct FusedArgs {
     const EventDesc* ev;
     EventResult* res;
     unsigned long long* tile_state;  // [n_ev * n_fed] decoupled look-back words
-    uint32_t* queue;                 // tile ticket counter
+    uint32_t* queue;                 // kQueueBytes of tile ticket counters
     DeviceCalib cal;
     uint32_t n_ev;
-    uint32_t fed_major;
+    uint32_t fed_major;              // tile order: 0 event-major, 1 FED-major, 2 FED-major per XCD
 };
 
 // Scratch of the allocation-free batch call (sc_process_events_static), a file-scope device
@@ -57,7 +62,7 @@ struct FusedArgs {
 constexpr size_t kStaticResOff = 0;
 constexpr size_t kStaticDescOff = kStaticResOff + sizeof(EventResult) * SC_STATIC_MAX_EVENTS;
 constexpr size_t kStaticQueueOff = (kStaticDescOff + sizeof(EventDesc) * SC_STATIC_MAX_EVENTS + 255) / 256 * 256;
-constexpr size_t kStaticStateOff = kStaticQueueOff + 256;
+constexpr size_t kStaticStateOff = kStaticQueueOff + kQueueBytes;
 constexpr size_t kStaticScratchBytes = kStaticStateOff + sizeof(unsigned long long) * SC_STATIC_MAX_TILES;
 // Device address of that array on the current device (hipGetSymbolAddress; once per device).
 hipError_t static_scratch_address(void** ptr);

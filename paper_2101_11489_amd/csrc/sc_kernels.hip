@@ -7,7 +7,9 @@
 // MI355X design (not the paper's CUDA design):
 //  * a workgroup of W wavefronts owns one (event, FED) tile at a time; a persistent grid pulls
 //    tiles from an atomic queue, FED-major (the events of one FED back to back, so its
-//    calibration is reused from cache) or event-major;
+//    calibration is reused from cache) or event-major, or from eight FED-major queues with the
+//    FEDs dealt round-robin, one queue per XCD (workgroup i runs on XCD i mod 8): the events of
+//    a FED then run on one XCD and its calibration is fetched into one L2, not eight;
 //  * the FED's bytes and gains are staged into LDS with all 16-byte loads in flight at once; wave
 //    0 walks the 96 length fields in LDS (the channel map the paper builds on the CPU); then each
 //    wave takes a group of 96/W channels on its own: one lane per channel validates the records
@@ -42,6 +44,7 @@ hipError_t static_scratch_address(void** ptr) {
 namespace {
 
 constexpr uint32_t kSpinLimit = 1u << 22;   // look-back wait bound (seconds of sleeping)
+constexpr uint32_t kXcds = 8;               // XCDs of the device (queues of tile order 2)
 constexpr int kNch = kChannelsPerFed;
 constexpr int kStripsPerFed = kChannelsPerFed * kStripsPerChannel;
 constexpr uint32_t kGainVecs = 2 * kNch / 4;   // a FED's APV gains as 16-byte vectors
@@ -1162,16 +1165,91 @@ __device__ __forceinline__ uint32_t next_tile(TileSmem<W, DW>& sm, uint32_t* que
     }
 }
 
-// Runs tile(e, f) for every tile of an n_ev x n_fed launch.
+// Tile order 2: G = min(8, grid) queues; queue x holds the FEDs f = x (mod G), FED-major, and
+// counts its tickets in queue[x * kQueueStride] (one cache line each). A workgroup takes tiles
+// from queue (blockIdx mod G), its home, until that is exhausted, then moves on to another open
+// queue; it ends once every queue is known to be exhausted. Returns the tile as f * n_ev + e, or
+// n_ev * n_fed at the end.
+// Look-back ends here too, if the whole grid is resident (the host launches this order only
+// with no other such launch running, and never with more workgroups than fit): take the unfinished
+// tile of lowest FED. Either it has been taken, and its predecessors (lower FEDs) are finished,
+// or it is still in its queue x; then queue x is not exhausted, so the workgroups of home x (at
+// least one, resident) hold only tiles of queue x taken before it, of FED at most its own,
+// which finish and take it next.
+struct XcdCursor {
+    uint32_t cur;     // the queue claimed from
+    uint32_t known;   // bit x: queue x is exhausted (a ticket past its end, or its counter seen so)
+};
+
+__device__ __forceinline__ uint32_t queue_tiles(uint32_t x, uint32_t n_ev, uint32_t n_fed,
+                                                uint32_t groups) {
+    return x < n_fed ? (n_fed - x + groups - 1u) / groups * n_ev : 0u;
+}
+
+__device__ __forceinline__ uint32_t claim_xcd(uint32_t* queue, uint32_t n_ev, uint32_t n_fed,
+                                              uint32_t groups, XcdCursor& c) {
+    const uint32_t all = (1u << groups) - 1u;
+    // each pass either returns a tile or adds a queue to `known`: at most groups + 1 passes
+    for (uint32_t k = 0; k <= groups && c.known != all; ++k) {
+        const uint32_t x = uni(c.cur);   // a scalar address: one atomic per wave, not per lane
+        const uint32_t size = queue_tiles(x, n_ev, n_fed, groups);
+        if (size && !(c.known >> x & 1u)) {
+            const uint32_t t = uni(atomicAdd(queue + x * kQueueStride, lane() == 0u ? 1u : 0u));
+            if (t < size) {
+                const uint32_t j = t / n_ev;
+                return (x + j * groups) * n_ev + (t - j * n_ev);
+            }
+        }
+        c.known |= 1u << x;
+        // the next queue not known to be exhausted, from the counters (lane i reads queue i's);
+        // a counter only grows, so one read at or past the end is final, and a stale lower read
+        // costs one more failed ticket
+        bool open = false;
+        if (lane() < groups && !(c.known >> lane() & 1u)) {
+            const uint32_t v = __hip_atomic_load(queue + lane() * kQueueStride, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            open = v < queue_tiles(lane(), n_ev, n_fed, groups);
+        }
+        const uint32_t m = (uint32_t)__ballot(open);
+        c.known = uni(c.known | (all & ~m));
+        if (!m) break;
+        const uint32_t after = m & ~((2u << x) - 1u);   // open queues past x, then from 0
+        c.cur = uni((uint32_t)__builtin_ctz(after ? after : m));
+    }
+    return n_ev * n_fed;
+}
+
+template <int W, int DW>
+__device__ __forceinline__ uint32_t next_tile_xcd(TileSmem<W, DW>& sm, uint32_t* queue,
+                                                  uint32_t n_ev, uint32_t n_fed, uint32_t groups,
+                                                  XcdCursor& cur) {
+    if constexpr (W == 1) {
+        return claim_xcd(queue, n_ev, n_fed, groups, cur);
+    } else {
+        if (wave_index<W>() == 0u) {
+            __builtin_amdgcn_s_setprio(3);
+            sm.walk[3] = claim_xcd(queue, n_ev, n_fed, groups, cur);
+            __builtin_amdgcn_s_setprio(0);
+        }
+        tile_sync();
+        return uni(sm.walk[3]);
+    }
+}
+
+// Runs tile(e, f) for every tile of an n_ev x n_fed launch, in tile order `order` (0 event-major,
+// 1 FED-major, 2 FED-major per XCD).
 template <int W, int DW, class TileFn>
 __device__ __forceinline__ void run_tiles(TileSmem<W, DW>& sm, uint32_t* queue, uint32_t n_ev,
-                                          uint32_t n_fed, uint32_t fed_major, TileFn tile) {
+                                          uint32_t n_fed, uint32_t order, TileFn tile) {
     const uint32_t n_tiles = n_ev * n_fed;
+    const uint32_t groups = gridDim.x < kXcds ? gridDim.x : kXcds;
+    XcdCursor cur{blockIdx.x % groups, 0u};
     for (;;) {
-        const uint32_t t = next_tile(sm, queue);
+        const uint32_t t = order == 2u ? next_tile_xcd(sm, queue, n_ev, n_fed, groups, cur)
+                                       : next_tile(sm, queue);
         if (t >= n_tiles) break;
         uint32_t e, f;
-        if (fed_major) { f = t / n_ev; e = t - f * n_ev; }
+        if (order) { f = t / n_ev; e = t - f * n_ev; }
         else           { e = t / n_fed; f = t - e * n_fed; }
         tile(e, f);
         tile_sync();   // the tile ends here for every lane of every wave (a convergent point)
@@ -1260,7 +1338,7 @@ __global__ void reset_kernel(unsigned long long* state, uint32_t n_state, uint32
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t k = i; k < n_state; k += stride) state[k] = 0ull;
     for (uint32_t k = i; k < n_ev; k += stride) res[k] = EventResult{0u, 0u, 0u, 0u};
-    if (i == 0) *queue = 0u;
+    if (i < kXcds) queue[i * kQueueStride] = 0u;
 }
 
 // Effective noise per strip: the noise itself, or +inf when the strip is unusable (bad flag,

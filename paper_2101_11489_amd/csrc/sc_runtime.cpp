@@ -99,7 +99,7 @@ struct Workspace {
         if ((e = desc.ensure(sizeof(EventDesc) * n_ev)) != hipSuccess) return e;
         if ((e = res.ensure(sizeof(EventResult) * n_ev)) != hipSuccess) return e;
         if ((e = state.ensure(sizeof(unsigned long long) * (size_t)n_ev * n_fed)) != hipSuccess) return e;
-        if ((e = queue.ensure(64)) != hipSuccess) return e;
+        if ((e = queue.ensure(kQueueBytes)) != hipSuccess) return e;
         if ((e = h_desc.ensure(sizeof(EventDesc) * n_ev)) != hipSuccess) return e;
         if ((e = h_res.ensure(sizeof(EventResult) * n_ev)) != hipSuccess) return e;
         if (old[0] != desc.p) desc_on_device.clear();
@@ -397,7 +397,7 @@ hipError_t enqueue_clean(sc_ctx* c, Workspace& ws, hipStream_t s) {
 // The device part of a batched launch: descriptors H2D (unless the device already holds the
 // same ones; always when capturing a graph), reset, fused kernel, results D2H.
 hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bool timed,
-                         bool capturing = false) {
+                         bool capturing = false, bool exclusive = true) {
     hipError_t e;
     const EventDesc* hd = ws.h_desc.as<EventDesc>();
     const bool same = !capturing && ws.desc_on_device.size() == n &&
@@ -407,7 +407,10 @@ hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bo
             return e;
         ws.desc_on_device.assign(hd, hd + n);
     }
-    const FusedArgs a = fused_args(c, ws, n);
+    FusedArgs a = fused_args(c, ws, n);
+    // the per-XCD order needs its whole grid resident with no other such launch running: only a
+    // launch that holds order2_mu to its end (the synchronous calls) uses it
+    if (!exclusive && a.fed_major == 2u) a.fed_major = 1u;
     if (capturing || !ws.clean) {
         if ((e = launch_reset(a, n * c->n_fed, s))) return e;
     }
@@ -482,11 +485,17 @@ sc_status finish_batch(sc_ctx* c, Workspace& ws, const Staged& st, uint32_t n, s
     return total;
 }
 
+// Held from the launch of a batch in tile order 2 (FED-major per XCD) until it has finished, in
+// this process: two such launches at once could each fill the XCDs the other's look-back needs.
+std::mutex order2_mu;
+
 sc_status run_batch(sc_ctx* c, const sc_event* ev, uint32_t n, sc_clusters* out,
                     sc_status* ev_status, bool allow_graph) {
     Staged st;
     sc_status s0 = stage_batch(c, c->ws, ev, n, out, c->stream, st);
     if (s0 != SC_OK) return s0;
+    std::unique_lock<std::mutex> excl(order2_mu, std::defer_lock);
+    if (c->tuning.fed_major == 2u) excl.lock();
     const bool graph = allow_graph && c->tuning.use_graph;
     if (graph) SC_HIP(c, enqueue_batch_graph(c, c->ws, n, c->stream));
     else       SC_HIP(c, enqueue_batch(c, c->ws, n, c->stream, true));
@@ -520,7 +529,7 @@ bool load_tuning(sc_ctx* c) {
     unsigned a = 0, w = 0, b = 0, d = 0, g = 0;
     if (std::sscanf(txt.c_str() + p, "[%u,%u,%u,%u,%u]", &a, &w, &b, &d, &g) != 5) return false;
     if (!tile_shape_supported(w, a) || b < 1 || b > 32) return false;
-    c->tuning = sc_tuning{a, w, b, d ? 1u : 0u, g ? 1u : 0u};
+    c->tuning = sc_tuning{a, w, b, d > 2u ? 1u : d, g ? 1u : 0u};
     return true;
 }
 
@@ -790,7 +799,7 @@ struct Server {
         hipError_t e = hipEventRecord(slot->t0, slot->s);
         sc_status st = e == hipSuccess ? stage_batch(c, slot->ws, evs.data(), n, outs.data(), slot->s, slot->st)
                                        : SC_ERR_DEVICE;
-        if (st == SC_OK) e = enqueue_batch(c, slot->ws, n, slot->s, false);
+        if (st == SC_OK) e = enqueue_batch(c, slot->ws, n, slot->s, false, false, false);
         if (st == SC_OK && e == hipSuccess) e = hipEventRecord(slot->done, slot->s);
         if (st != SC_OK || e != hipSuccess) {
             if (e != hipSuccess) device_fail(c, e, "server launch");
@@ -927,7 +936,7 @@ sc_status sc_create(const sc_calib* cal, const sc_options* opt_in, sc_ctx** out)
         return fail(nullptr, SC_ERR_DEVICE, "hipGetDeviceProperties");
     c->n_cu = prop.multiProcessorCount;
     c->device_name = prop.gcnArchName;
-    c->tuning = sc_tuning{2880, 2, 32, 1, 1};
+    c->tuning = sc_tuning{2880, 2, 32, 2, 1};
     load_tuning(c.get());
     if (opt.stream) {
         c->stream = static_cast<hipStream_t>(opt.stream);
@@ -1146,6 +1155,8 @@ sc_status sc_process_events_static(sc_ctx* c, const sc_event* ev, uint32_t n, sc
     hipStream_t s = c->stream;
     SC_HIP(c, hipMemcpyAsync(const_cast<EventDesc*>(a.ev), hd, sizeof(EventDesc) * n,
                              hipMemcpyHostToDevice, s));
+    std::unique_lock<std::mutex> excl(order2_mu, std::defer_lock);
+    if (a.fed_major == 2u) excl.lock();
     // the array keeps the last call's contents: clear the look-back words, queue and results
     SC_HIP(c, launch_reset(a, n * c->n_fed, s));
     SC_HIP(c, hipEventRecord(c->ev0, s));
@@ -1290,7 +1301,7 @@ sc_status sc_set_tuning(sc_ctx* c, const sc_tuning* t) {
                     "unsupported tuning (tile_waves 1, 2 or 4; chunk_digis 2048, 3072 or 4096, "
                     "1024 with one wave, 2880 with two)");
     c->tuning = *t;
-    c->tuning.fed_major = t->fed_major ? 1 : 0;
+    c->tuning.fed_major = t->fed_major > 2u ? 1u : t->fed_major;
     c->tuning.use_graph = t->use_graph ? 1 : 0;
     return SC_OK;
 }
@@ -1339,7 +1350,7 @@ sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best
     std::vector<sc_tuning> cands;
     for (uint32_t w : {1u, 2u, 4u})
         for (uint32_t d : {1024u, 2048u, 2880u, 3072u, 4096u})
-            for (uint32_t fm : {0u, 1u})
+            for (uint32_t fm : {0u, 1u, 2u})
                 if (tile_shape_supported(w, d)) cands.push_back(sc_tuning{d, w, 32, fm, 0});
     const size_t n_stage1 = cands.size();
     std::vector<uint8_t> ref_cl, ref_adc, cur_cl, cur_adc;

@@ -50,6 +50,24 @@ def test_full_detector_batch_exact(full, waves, chunk):
         ctx.tuning = before
 
 
+@pytest.mark.parametrize("waves,chunk", [(2, 2880), (1, 3072)])
+@pytest.mark.parametrize("graph", [0, 1])
+def test_full_detector_per_xcd_order_exact(full, waves, chunk, graph):
+    """Tile order 2 (FEDs dealt to one queue per XCD): the 8 full-size events, eager and as graph
+    replays, several times in a row, give the oracle's clusters."""
+    cal, evs, refs, ctx = full
+    before = ctx.tuning
+    ctx.tuning = {"use_graph": graph, "tile_waves": waves, "chunk_digis": chunk, "fed_major": 2}
+    try:
+        for rep in range(3):
+            results, rc, _, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs])
+            assert rc == sc.SC_OK
+            for i, (res, ref) in enumerate(zip(results, refs)):
+                compare_clusters(res[0], res[1], ref, f"order 2 call {rep} event {i}")
+    finally:
+        ctx.tuning = before
+
+
 def test_event_alone_equals_event_in_any_batch(full):
     cal, evs, refs, ctx = full
     pairs = [(e.zs, e.fed_offset) for e in evs]
@@ -245,6 +263,25 @@ def test_server_matches_oracle_and_is_mix_independent(full):
         assert st["server_events"] == len(evs) + 1 and st["server_batches"] >= 2
         assert ctx.poll(t, 0) == sc.SC_ERR_UNKNOWN_TICKET
         assert ctx.poll(123456789, 0) == sc.SC_ERR_UNKNOWN_TICKET
+
+
+def test_server_under_per_xcd_tuning(full):
+    """A context tuned to tile order 2 serves with order 1 (several server launches may run at
+    once); results are the oracle's, and synchronous calls on it keep order 2."""
+    cal, evs, refs, _ = full
+    with make_ctx(cal.noise, cal.gain, cal.bad, max_batch=3, n_streams=2) as ctx:
+        ctx.tuning = {"fed_major": 2, "use_graph": 0}
+        devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs]
+        outs = [ctx.output(*sc.safe_caps(d)) for d in devs]
+        tickets = [ctx.submit(d, o) for d, o in zip(devs, outs)]
+        for t in tickets:
+            assert ctx.poll(t, -1) == sc.SC_OK
+        for i, (o, ref) in enumerate(zip(outs, refs)):
+            compare_clusters(*o.to_numpy()[:2], ref, f"served under order 2, event {i}")
+        assert ctx.tuning["fed_major"] == 2
+        results, rc, _, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs[:3]])
+        for r, ref in zip(results, refs[:3]):
+            compare_clusters(r[0], r[1], ref, "synchronous after serving")
 
 
 def test_server_budget_and_backpressure(full):

@@ -142,7 +142,7 @@ SHAPES = [(1, 1024), (1, 2048), (1, 3072), (1, 4096), (2, 2048), (2, 2880), (2, 
 
 
 @pytest.mark.parametrize("waves,chunk", SHAPES, ids=[f"w{w}-d{d}" for w, d in SHAPES])
-@pytest.mark.parametrize("fed_major", [0, 1])
+@pytest.mark.parametrize("fed_major", [0, 1, 2])
 def test_tuning_choices_identical(cfg0, waves, chunk, fed_major):
     cfg, cal, evs, ctx = cfg0
     refs = [oracle.process_event(e.zs, e.fed_offset, cal.noise, cal.gain, cal.bad) for e in evs[:3]]
