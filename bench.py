@@ -266,6 +266,52 @@ def plain_line(sc, torch, stream, cfg_id, n_events, workers, tuning):
     }
 
 
+def ingest_line(sc, torch, ctx, events, outs, batch, reps):
+    """Events/s with host-resident inputs, the host link included: sc_process_pipelined over
+    reps x the batch's events (page-locked, then pageable inputs), beside the same batches one
+    sc_process_events call at a time (transfer, then compute) and the measured link rate."""
+    pageable = [sc.Event(e.zs, e.fed_offset) for e in events]
+    pinned = sc.pack_pinned(pageable)             # back to back, as in a readout ring
+    scattered = [e.to_pinned() for e in pageable]  # one page-locked buffer per event
+    n = len(events)
+    zs_bytes = sum(int(e.zs.size) + 8 * (len(e.fed_offset)) for e in events)
+    out_all = outs * reps
+
+    def timed(fn, k=3):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(k):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    t_pin = timed(lambda: ctx.process_pipelined(pinned * reps, out_all, batch))
+    t_scat = timed(lambda: ctx.process_pipelined(scattered * reps, out_all, batch))
+    t_page = timed(lambda: ctx.process_pipelined(pageable * reps, out_all, batch))
+    t_serial = timed(lambda: [ctx.process_events(pinned, outs) for _ in range(reps)])
+    # the link alone: the same bytes, page-locked host to device, one copy
+    src = torch.empty(zs_bytes, dtype=torch.uint8, pin_memory=True)
+    dst = torch.empty(zs_bytes, dtype=torch.uint8, device="cuda")
+    t_link = timed(lambda: [dst.copy_(src, non_blocking=True) for _ in range(reps)])
+    ev_total = n * reps
+    return {
+        "workload": f"{ev_total} full-detector events ({reps} x the batch's {n}) from host memory "
+                    f"in batches of {batch}, device outputs; pinned: the events back to back in "
+                    "one page-locked buffer; scattered: one page-locked buffer per event",
+        "pipelined_pinned_events_per_s": ev_total / t_pin,
+        "pipelined_pinned_scattered_events_per_s": ev_total / t_scat,
+        "pipelined_pageable_events_per_s": ev_total / t_page,
+        "serial_pinned_events_per_s": ev_total / t_serial,
+        "link_h2d_gbs": reps * zs_bytes / t_link / 1e9,
+        "link_bound_events_per_s": ev_total / t_link,
+        "host_bytes_per_event": zs_bytes / n,
+        "best_of": 3,
+    }
+
+
 def stress_line(sc, torch, stream, workers, tuning, cap_cl, cap_adc, steps):
     """The 256-event stress batch at full size: one launch with output capacities sized for the
     64-event batch (overflows are reported with the needed sizes), then the batch again with
@@ -394,6 +440,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-stress", action="store_true")
     ap.add_argument("--no-cold", action="store_true")
+    ap.add_argument("--no-ingest", action="store_true")
     ap.add_argument("--serve-events", type=int, default=2000,
                     help="events per arrival-rate point of the serving sweep")
     ap.add_argument("--tuning", default=None,
@@ -531,6 +578,13 @@ def main():
             log(f"plain config {cid}: {plain[f'config{cid}']}")
 
     # ---- the 256-event stress batch ------------------------------------------------------------
+    ingest = None
+    if not args.no_ingest:
+        ctx.tuning = {"use_graph": 0}
+        ingest = ingest_line(sc, torch, ctx, events, outs, n_ev, 8)
+        ctx.tuning = {"use_graph": 1}
+        log(f"host ingest: {ingest}")
+
     stress = None
     if not args.no_stress:
         cap_cl = max(c for c, _ in counts)
@@ -584,6 +638,7 @@ def main():
         "eager": eager,
         "cache_cold": cold,
         "plain_path": plain or None,
+        "host_ingest": ingest,
         "stress": stress,
         "serving": serving,
         "cpu_baseline": cpu,

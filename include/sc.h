@@ -76,7 +76,12 @@ typedef enum {
     SC_ERR_UNKNOWN_TICKET = -7 /* sc_poll: ticket never issued or already collected */
 } sc_status;
 
-typedef enum { SC_MEM_HOST = 0, SC_MEM_DEVICE = 1 } sc_mem;
+/* Memory kinds. SC_MEM_HOST_PINNED is host memory the caller page-locked (hipHostMalloc, or a
+ * torch tensor made with pin_memory=True): events in it are copied to the device by DMA straight
+ * from the caller's buffer, where SC_MEM_HOST events are first copied into the library's pinned
+ * staging by the CPU. It is an event kind (sc_event.mem) only; outputs are SC_MEM_HOST or
+ * SC_MEM_DEVICE. */
+typedef enum { SC_MEM_HOST = 0, SC_MEM_DEVICE = 1, SC_MEM_HOST_PINNED = 2 } sc_mem;
 
 typedef struct sc_ctx sc_ctx;
 
@@ -107,7 +112,8 @@ typedef struct {
     const char *tune_cache;/* autotuner cache file (JSON); NULL: none */
 } sc_options;
 
-/* One event: its FED buffers and FED offsets (u64 [n_fed+1], fed_offset[0] is usually 0). */
+/* One event: its FED buffers and FED offsets (u64 [n_fed+1], fed_offset[0] is usually 0), both in
+ * memory kind mem (any of the three). */
 typedef struct {
     const uint8_t *zs;
     const uint64_t *fed_offset;
@@ -203,6 +209,20 @@ sc_status sc_cluster(sc_ctx *ctx, const uint8_t *adc_dense, sc_mem in_mem, sc_cl
  * do not depend on the other events of the batch. */
 sc_status sc_process_events(sc_ctx *ctx, const sc_event *ev, uint32_t n, sc_clusters *out,
                             sc_status *ev_status);
+
+/* Host ingest overlapped with compute (§2: the channel map can be built while the raw data is
+ * transferred; §3: communication overlapped with computation). Processes n events as consecutive
+ * batches of `batch` events, each one fused launch as in sc_process_events: while batch k runs on
+ * the context's stream, batch k+1 is staged (SC_MEM_HOST events copied into pinned staging by the
+ * CPU; SC_MEM_HOST_PINNED events need no copy) and sent to the device on a second stream; host
+ * outputs come back on a third. Page-locked events that lie back to back in host memory (each
+ * starting where the previous one's last FED ends) go over in one transfer, which keeps the link
+ * busy; scattered ones take one transfer each. Two staging slots alternate, sized for the
+ * largest batch on entry. Results, ev_status[i] (optional) and the return value as for sc_process_events over all
+ * n events; SC_ERR_INVALID_ARG for n == 0 or batch == 0. Synchronous: every event is done on
+ * return, and its buffers may be reused. */
+sc_status sc_process_pipelined(sc_ctx *ctx, const sc_event *ev, uint32_t n, sc_clusters *out,
+                               uint32_t batch, sc_status *ev_status);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): sc_process_events without any allocation. Every event

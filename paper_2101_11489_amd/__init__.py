@@ -25,7 +25,7 @@ SC_OK, SC_MALFORMED, SC_PENDING = 0, 1, 2
 SC_ERR_INVALID_ARG, SC_ERR_OVERFLOW, SC_ERR_BUDGET = -1, -2, -3
 SC_STATIC_MAX_EVENTS, SC_STATIC_MAX_TILES = 1024, 1024 * 440   # sc_process_events_static
 SC_ERR_AGAIN, SC_ERR_DEVICE, SC_ERR_NOMEM, SC_ERR_UNKNOWN_TICKET = -4, -5, -6, -7
-SC_MEM_HOST, SC_MEM_DEVICE = 0, 1
+SC_MEM_HOST, SC_MEM_DEVICE, SC_MEM_HOST_PINNED = 0, 1, 2
 CH_MALFORMED, CH_FED_TRAILING = 1, 2
 
 STATUS_NAMES = {0: "OK", 1: "MALFORMED", 2: "PENDING", -1: "INVALID_ARG", -2: "OVERFLOW",
@@ -35,7 +35,7 @@ CLUSTER_DTYPE = np.dtype([("channel", "<u4"), ("first", "<u2"), ("width", "<u2")
                           ("charge", "<u4"), ("barycenter", "<f4")])
 
 EXPORTED = ["sc_default_options", "sc_create", "sc_destroy", "sc_unpack", "sc_cluster",
-            "sc_process_events", "sc_process_events_static", "sc_submit", "sc_poll", "sc_serve_replay", "sc_get_tuning",
+            "sc_process_events", "sc_process_pipelined", "sc_process_events_static", "sc_submit", "sc_poll", "sc_serve_replay", "sc_get_tuning",
             "sc_set_tuning", "sc_autotune", "sc_get_stats", "sc_last_error"]
 
 
@@ -105,6 +105,9 @@ def lib():
             "sc_cluster": ([P, P, ctypes.c_int, ctypes.POINTER(ScClusters)], st),
             "sc_process_events": ([P, ctypes.POINTER(ScEvent), ctypes.c_uint32,
                                    ctypes.POINTER(ScClusters), ctypes.POINTER(ctypes.c_int)], st),
+            "sc_process_pipelined": ([P, ctypes.POINTER(ScEvent), ctypes.c_uint32,
+                                      ctypes.POINTER(ScClusters), ctypes.c_uint32,
+                                      ctypes.POINTER(ctypes.c_int)], st),
             "sc_process_events_static": ([P, ctypes.POINTER(ScEvent), ctypes.c_uint32,
                                           ctypes.POINTER(ScClusters), ctypes.POINTER(ctypes.c_int)],
                                          st),
@@ -153,9 +156,11 @@ def _is_dev(x) -> bool:
 @dataclass
 class Event:
     """One event: ZS bytes and FED offsets (u64 [n_fed+1]), both numpy (host) or both torch
-    CUDA tensors (device)."""
+    CUDA tensors (device). pinned=True marks numpy arrays that view page-locked memory (made by
+    to_pinned), which the library copies to the device without staging."""
     zs: object
     fed_offset: object
+    pinned: bool = False
 
     def __post_init__(self):
         if isinstance(self.zs, np.ndarray):
@@ -167,7 +172,23 @@ class Event:
 
     @property
     def mem(self) -> int:
-        return SC_MEM_DEVICE if _is_dev(self.zs) else SC_MEM_HOST
+        if _is_dev(self.zs):
+            return SC_MEM_DEVICE
+        return SC_MEM_HOST_PINNED if self.pinned else SC_MEM_HOST
+
+    def to_pinned(self) -> "Event":
+        """A host copy in page-locked memory (torch pin_memory), kept alive by the Event."""
+        torch = _torch()
+        zs = np.ascontiguousarray(self.zs, dtype=np.uint8)
+        fo = np.ascontiguousarray(self.fed_offset, dtype=np.uint64)
+        tz = torch.empty(max(zs.size, 1), dtype=torch.uint8, pin_memory=True)
+        tf = torch.empty(fo.size, dtype=torch.int64, pin_memory=True)
+        nz, nf = tz.numpy()[:zs.size], tf.numpy().view(np.uint64)
+        nz[:] = zs
+        nf[:] = fo
+        ev = Event(nz, nf, pinned=True)
+        ev._pinned_keep = (tz, tf)
+        return ev
 
     def c(self) -> ScEvent:
         zs = self.zs
@@ -181,6 +202,30 @@ class Event:
         zs = torch.from_numpy(np.ascontiguousarray(self.zs, dtype=np.uint8)).to(device)
         fo = torch.from_numpy(np.ascontiguousarray(self.fed_offset, dtype=np.uint64).view(np.int64)).to(device)
         return Event(zs, fo)
+
+
+def pack_pinned(events):
+    """Host copies of the events laid back to back in one page-locked buffer (the layout of a
+    readout ring): consecutive events of a batch then go to the device in one transfer."""
+    torch = _torch()
+    zs = [np.ascontiguousarray(e.zs, dtype=np.uint8) for e in events]
+    spans = [int(np.asarray(e.fed_offset, dtype=np.uint64).max()) if len(e.fed_offset) else 0
+             for e in events]
+    if any(sp > z.size for sp, z in zip(spans, zs)):
+        raise ValueError("an event's FED offsets reach past its bytes")
+    total = sum(spans)
+    buf = torch.empty(max(total, 1), dtype=torch.uint8, pin_memory=True)
+    flat = buf.numpy()
+    out, at = [], 0
+    for e, z, sp in zip(events, zs, spans):
+        flat[at:at + sp] = z[:sp]
+        fo = torch.empty(len(e.fed_offset), dtype=torch.int64, pin_memory=True)
+        fo.numpy().view(np.uint64)[:] = np.asarray(e.fed_offset, dtype=np.uint64)
+        ev = Event(flat[at:at + sp], fo.numpy().view(np.uint64), pinned=True)
+        ev._pinned_keep = (buf, fo)
+        out.append(ev)
+        at += sp
+    return out
 
 
 class Batch:
@@ -352,6 +397,20 @@ class Context:
         sts = (ctypes.c_int * n)()
         self._order()
         rc = lib().sc_process_events(self._h, evs, n, cs, sts)
+        for o, c in zip(outs, cs):
+            o.cs.n_cl, o.cs.n_adc = c.n_cl, c.n_adc
+        self._check(rc, (SC_OK, SC_MALFORMED, SC_ERR_OVERFLOW))
+        return rc, list(sts)
+
+    def process_pipelined(self, events, outs, batch):
+        """Host ingest overlapped with compute: the events as consecutive batches of `batch`,
+        batch k+1 sent to the device while batch k runs. Returns (status, per-event statuses)."""
+        n = len(events)
+        evs = (ScEvent * n)(*[e.c() for e in events])
+        cs = (ScClusters * n)(*[o.cs for o in outs])
+        sts = (ctypes.c_int * n)()
+        self._order()
+        rc = lib().sc_process_pipelined(self._h, evs, n, cs, batch, sts)
         for o, c in zip(outs, cs):
             o.cs.n_cl, o.cs.n_adc = c.n_cl, c.n_adc
         self._check(rc, (SC_OK, SC_MALFORMED, SC_ERR_OVERFLOW))

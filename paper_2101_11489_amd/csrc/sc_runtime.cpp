@@ -171,6 +171,11 @@ struct sc_ctx {
     // host memory for its descriptors and results (both set up by sc_create)
     uint8_t* d_static = nullptr;
     PinBuf h_static;
+    // sc_process_pipelined: two staging slots, a stream for the transfers to the device and one
+    // for host outputs coming back (made on first use)
+    Workspace pipe_ws[2];
+    hipStream_t pipe_h2d = nullptr, pipe_d2h = nullptr;
+    hipEvent_t pipe_in[2] = {nullptr, nullptr}, pipe_done[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -244,12 +249,16 @@ void record_kernel_ms(sc_ctx* c) {
     }
 }
 
+// Event bytes in host memory: pageable (copied through pinned staging) or page-locked by the
+// caller (copied by DMA straight from its buffer).
+bool host_mem(int m) { return m == SC_MEM_HOST || m == SC_MEM_HOST_PINNED; }
+
 sc_status check_event(sc_ctx* c, const sc_event& ev) {
-    if (!ev.zs && ev.mem == SC_MEM_HOST) return fail(c, SC_ERR_INVALID_ARG, "event zs is NULL");
+    if (!ev.zs && host_mem(ev.mem)) return fail(c, SC_ERR_INVALID_ARG, "event zs is NULL");
     if (!ev.fed_offset) return fail(c, SC_ERR_INVALID_ARG, "event fed_offset is NULL");
-    if (ev.mem != SC_MEM_HOST && ev.mem != SC_MEM_DEVICE)
+    if (!host_mem(ev.mem) && ev.mem != SC_MEM_DEVICE)
         return fail(c, SC_ERR_INVALID_ARG, "event mem kind");
-    if (ev.mem == SC_MEM_HOST && event_span(ev.fed_offset, c->n_fed) > kMaxEventBytes)
+    if (host_mem(ev.mem) && event_span(ev.fed_offset, c->n_fed) > kMaxEventBytes)
         return fail(c, SC_ERR_INVALID_ARG, "event larger than 2 GiB");
     return SC_OK;
 }
@@ -289,25 +298,41 @@ struct Staged {
     std::vector<uint64_t> cl_off, adc_off, st_off;   // host-output staging offsets
 };
 
+// Host events to the device on stream s, host-output staging, and the batch's descriptors (on
+// the host, for enqueue_batch).
+// Event i is page-locked and starts in host memory where page-locked event i - 1 ends.
+bool continues_pinned_run(const sc_event* ev, uint32_t i, uint32_t n_fed) {
+    return i > 0 && ev[i].mem == SC_MEM_HOST_PINNED && ev[i - 1].mem == SC_MEM_HOST_PINNED &&
+           ev[i].zs == ev[i - 1].zs + event_span(ev[i - 1].fed_offset, n_fed);
+}
+
 sc_status stage_batch(sc_ctx* c, Workspace& ws, const sc_event* ev, uint32_t n,
                       const sc_clusters* out, hipStream_t s, Staged& st) {
     const uint32_t n_fed = c->n_fed;
     SC_HIP(c, ws.ensure_batch(n, n_fed));
     // host inputs -> pinned -> device
     uint64_t zs_bytes = 0, fo_bytes = 0;
+    bool any_pageable = false;
+    for (uint32_t i = 0; i < n; ++i) any_pageable |= ev[i].mem == SC_MEM_HOST;
     st.zs_off.assign(n, 0);
     st.fo_off.assign(n, 0);
     for (uint32_t i = 0; i < n; ++i) {
-        if (ev[i].mem == SC_MEM_HOST) {
-            st.zs_off[i] = zs_bytes;
-            zs_bytes += align_up(event_span(ev[i].fed_offset, n_fed), 16);
+        if (host_mem(ev[i].mem)) {
+            // a page-locked event that starts where the previous one ends in host memory is
+            // staged right after it too, so that the run goes over in one transfer
+            if (continues_pinned_run(ev, i, n_fed)) {
+                st.zs_off[i] = st.zs_off[i - 1] + event_span(ev[i - 1].fed_offset, n_fed);
+            } else {
+                st.zs_off[i] = zs_bytes;
+            }
+            zs_bytes = align_up(st.zs_off[i] + event_span(ev[i].fed_offset, n_fed), 16);
             st.fo_off[i] = fo_bytes;
             fo_bytes += align_up(sizeof(uint64_t) * (n_fed + 1), 16);
         }
     }
     if (zs_bytes) {
         SC_HIP(c, ws.zs.ensure(zs_bytes));
-        SC_HIP(c, ws.h_zs.ensure(zs_bytes));
+        if (any_pageable) SC_HIP(c, ws.h_zs.ensure(zs_bytes));
     }
     if (fo_bytes) {
         SC_HIP(c, ws.fo.ensure(fo_bytes));
@@ -336,9 +361,10 @@ sc_status stage_batch(sc_ctx* c, Workspace& ws, const sc_event* ev, uint32_t n,
     EventDesc* hd = ws.h_desc.as<EventDesc>();
     for (uint32_t i = 0; i < n; ++i) {
         EventDesc d{};
-        if (ev[i].mem == SC_MEM_HOST) {
+        if (host_mem(ev[i].mem)) {
             const uint64_t span = event_span(ev[i].fed_offset, n_fed);
-            if (span) std::memcpy(ws.h_zs.as<uint8_t>() + st.zs_off[i], ev[i].zs, span);
+            if (span && ev[i].mem == SC_MEM_HOST)
+                std::memcpy(ws.h_zs.as<uint8_t>() + st.zs_off[i], ev[i].zs, span);
             std::memcpy(ws.h_fo.as<uint8_t>() + st.fo_off[i], ev[i].fed_offset,
                         sizeof(uint64_t) * (n_fed + 1));
             d.zs = ws.zs.as<uint8_t>() + st.zs_off[i];
@@ -360,7 +386,37 @@ sc_status stage_batch(sc_ctx* c, Workspace& ws, const sc_event* ev, uint32_t n,
         d.cap_adc = out[i].cap_adc;
         hd[i] = d;
     }
-    if (zs_bytes) SC_HIP(c, hipMemcpyAsync(ws.zs.p, ws.h_zs.p, zs_bytes, hipMemcpyHostToDevice, s));
+    // pageable events through the staging copy, one transfer per run of consecutive pageable
+    // events (so that no transfer covers a page-locked event's range); page-locked ones straight
+    // from the caller's buffers
+    for (uint32_t i = 0; i < n && any_pageable;) {
+        if (ev[i].mem != SC_MEM_HOST) {
+            ++i;
+            continue;
+        }
+        uint32_t j = i;
+        while (j < n && ev[j].mem == SC_MEM_HOST) ++j;
+        const uint64_t lo = st.zs_off[i];
+        const uint64_t hi = st.zs_off[j - 1] + event_span(ev[j - 1].fed_offset, n_fed);
+        if (hi > lo)
+            SC_HIP(c, hipMemcpyAsync(ws.zs.as<uint8_t>() + lo, ws.h_zs.as<uint8_t>() + lo, hi - lo,
+                                     hipMemcpyHostToDevice, s));
+        i = j;
+    }
+    for (uint32_t i = 0; i < n;) {
+        if (ev[i].mem != SC_MEM_HOST_PINNED) {
+            ++i;
+            continue;
+        }
+        uint32_t j = i + 1;
+        while (j < n && continues_pinned_run(ev, j, n_fed)) ++j;
+        const uint64_t lo = st.zs_off[i];
+        const uint64_t hi = st.zs_off[j - 1] + event_span(ev[j - 1].fed_offset, n_fed);
+        if (hi > lo)
+            SC_HIP(c, hipMemcpyAsync(ws.zs.as<uint8_t>() + lo, ev[i].zs, hi - lo,
+                                     hipMemcpyHostToDevice, s));
+        i = j;
+    }
     if (fo_bytes) SC_HIP(c, hipMemcpyAsync(ws.fo.p, ws.h_fo.p, fo_bytes, hipMemcpyHostToDevice, s));
     return SC_OK;
 }
@@ -662,7 +718,7 @@ struct Server {
                  devbuf_size(align_up(sizeof(uint16_t) * (size_t)o.cap_adc, 256));
             if (o.chan_status) b += devbuf_size(align_up((size_t)c->n_fed * kChannelsPerFed, 256));
         }
-        if (ev.mem == SC_MEM_HOST)
+        if (host_mem(ev.mem))
             b += devbuf_size(align_up(event_span(ev.fed_offset, c->n_fed), 16)) +
                  devbuf_size(align_up(sizeof(uint64_t) * (c->n_fed + 1), 16));
         return b;
@@ -673,7 +729,7 @@ struct Server {
                             const std::vector<sc_clusters>& outs) const {
         size_t zs = 0, fo = 0, cl = 0, adc = 0, st = 0;
         for (size_t i = 0; i < evs.size(); ++i) {
-            if (evs[i].mem == SC_MEM_HOST) {
+            if (host_mem(evs[i].mem)) {
                 zs += align_up(event_span(evs[i].fed_offset, c->n_fed), 16);
                 fo += align_up(sizeof(uint64_t) * (c->n_fed + 1), 16);
             }
@@ -698,12 +754,13 @@ struct Server {
             return fail(c, SC_ERR_BUDGET, "event larger than the HBM budget");
         r->ev = ev;
         r->out = out;
-        if (ev.mem == SC_MEM_HOST) {
+        if (host_mem(ev.mem)) {
             const uint64_t span = event_span(ev.fed_offset, c->n_fed);
             r->zs_copy.assign(ev.zs, ev.zs + span);
             r->fo_copy.assign(ev.fed_offset, ev.fed_offset + c->n_fed + 1);
             r->ev.zs = r->zs_copy.data();
             r->ev.fed_offset = r->fo_copy.data();
+            r->ev.mem = SC_MEM_HOST;   // the copy is pageable
         }
         r->t_submit = std::chrono::steady_clock::now();
         {
@@ -986,6 +1043,14 @@ void sc_destroy(sc_ctx* c) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->ws.release();
     c->h_static.release();
+    if (c->pipe_h2d) (void)hipStreamSynchronize(c->pipe_h2d);
+    for (int j = 0; j < 2; ++j) {
+        c->pipe_ws[j].release();
+        if (c->pipe_in[j]) (void)hipEventDestroy(c->pipe_in[j]);
+        if (c->pipe_done[j]) (void)hipEventDestroy(c->pipe_done[j]);
+    }
+    if (c->pipe_h2d) (void)hipStreamDestroy(c->pipe_h2d);
+    if (c->pipe_d2h) (void)hipStreamDestroy(c->pipe_d2h);
     if (c->d_noise) (void)hipFree(c->d_noise);
     if (c->d_gain) (void)hipFree(c->d_gain);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -1013,7 +1078,7 @@ sc_status sc_unpack(sc_ctx* c, const sc_event* ev, uint8_t* adc_dense, uint8_t* 
     SC_HIP(c, ws.ensure_batch(1, c->n_fed));
     const uint8_t* zs = ev->zs;
     const uint64_t* fo = ev->fed_offset;
-    if (ev->mem == SC_MEM_HOST) {
+    if (host_mem(ev->mem)) {
         const uint64_t span = event_span(ev->fed_offset, c->n_fed);
         SC_HIP(c, ws.zs.ensure(span + 16));
         SC_HIP(c, ws.fo.ensure(sizeof(uint64_t) * (c->n_fed + 1)));
@@ -1112,6 +1177,100 @@ sc_status sc_process_events(sc_ctx* c, const sc_event* ev, uint32_t n, sc_cluste
     }
     SC_HIP(c, hipSetDevice(c->device));
     return run_batch(c, ev, n, out, ev_status, all_device);
+}
+
+sc_status sc_process_pipelined(sc_ctx* c, const sc_event* ev, uint32_t n, sc_clusters* out,
+                               uint32_t batch, sc_status* ev_status) {
+    if (!c) return SC_ERR_INVALID_ARG;
+    if (c->poisoned) return SC_ERR_DEVICE;
+    if (!ev || !out || n == 0 || batch == 0)
+        return fail(c, SC_ERR_INVALID_ARG, "NULL argument, n == 0 or batch == 0");
+    if ((uint64_t)batch * c->n_fed > 0x7fffffffull) return fail(c, SC_ERR_INVALID_ARG, "batch too large");
+    for (uint32_t i = 0; i < n; ++i) {
+        sc_status s = check_event(c, ev[i]);
+        if (s != SC_OK) return s;
+        s = check_out(c, out[i]);
+        if (s != SC_OK) return s;
+    }
+    SC_HIP(c, hipSetDevice(c->device));
+    if (!c->pipe_h2d) {
+        SC_HIP(c, hipStreamCreateWithFlags(&c->pipe_h2d, hipStreamNonBlocking));
+        SC_HIP(c, hipStreamCreateWithFlags(&c->pipe_d2h, hipStreamNonBlocking));
+        for (int j = 0; j < 2; ++j) {
+            SC_HIP(c, hipEventCreateWithFlags(&c->pipe_in[j], hipEventDisableTiming));
+            SC_HIP(c, hipEventCreateWithFlags(&c->pipe_done[j], hipEventDisableTiming));
+        }
+    }
+    const uint32_t nb = (n + batch - 1) / batch;
+    // both slots sized for the largest batch first: a buffer that moved later would be freed,
+    // and a free waits for the whole device
+    uint64_t zs_max = 0, fo_max = 0, cl_max = 0, adc_max = 0, st_max = 0;
+    bool pageable = false;
+    for (uint32_t k = 0; k < nb; ++k) {
+        uint64_t zs = 0, fo = 0, cl = 0, adc = 0, st = 0;
+        for (uint32_t i = k * batch; i < std::min(n, (k + 1) * batch); ++i) {
+            if (host_mem(ev[i].mem)) {
+                zs += align_up(event_span(ev[i].fed_offset, c->n_fed), 16);
+                fo += align_up(sizeof(uint64_t) * (c->n_fed + 1), 16);
+                pageable |= ev[i].mem == SC_MEM_HOST;
+            }
+            if (out[i].mem == SC_MEM_HOST) {
+                cl += align_up(sizeof(sc_cluster_rec) * (uint64_t)out[i].cap_cl, 256);
+                adc += align_up(sizeof(uint16_t) * (uint64_t)out[i].cap_adc, 256);
+                if (out[i].chan_status) st += align_up((uint64_t)c->n_fed * kChannelsPerFed, 256);
+            }
+        }
+        zs_max = std::max(zs_max, zs);
+        fo_max = std::max(fo_max, fo);
+        cl_max = std::max(cl_max, cl);
+        adc_max = std::max(adc_max, adc);
+        st_max = std::max(st_max, st);
+    }
+    for (Workspace& ws : c->pipe_ws) {
+        SC_HIP(c, ws.ensure_batch(std::min(n, batch), c->n_fed));
+        if (zs_max) SC_HIP(c, ws.zs.ensure(zs_max));
+        if (zs_max && pageable) SC_HIP(c, ws.h_zs.ensure(zs_max));
+        if (fo_max) SC_HIP(c, ws.fo.ensure(fo_max));
+        if (fo_max) SC_HIP(c, ws.h_fo.ensure(fo_max));
+        if (cl_max) SC_HIP(c, ws.cl.ensure(cl_max));
+        if (adc_max) SC_HIP(c, ws.adc.ensure(adc_max));
+        if (st_max) SC_HIP(c, ws.chst.ensure(st_max));
+    }
+    std::unique_lock<std::mutex> excl(order2_mu, std::defer_lock);
+    if (c->tuning.fed_major == 2u) excl.lock();
+    Staged staged[2];
+    sc_status total = SC_OK;
+    // batch k's results: its kernel and results copy are done once pipe_done[k % 2] is
+    auto finish = [&](uint32_t k) -> sc_status {
+        const uint32_t j = k & 1u, i0 = k * batch, m = std::min(batch, n - i0);
+        SC_HIP(c, hipEventSynchronize(c->pipe_done[j]));
+        return finish_batch(c, c->pipe_ws[j], staged[j], m, out + i0,
+                            ev_status ? ev_status + i0 : nullptr, c->pipe_d2h);
+    };
+    for (uint32_t k = 0; k < nb; ++k) {
+        const uint32_t j = k & 1u, i0 = k * batch, m = std::min(batch, n - i0);
+        if (k >= 2) {   // slot j's previous batch (k - 2) must be done before its buffers refill
+            const sc_status fs = finish(k - 2);
+            if (fs == SC_ERR_DEVICE) return fs;
+            total = worst(total, fs);
+        }
+        // host staging and the copies to the device run while batch k - 1 computes
+        Workspace& ws = c->pipe_ws[j];
+        const sc_status s0 = stage_batch(c, ws, ev + i0, m, out + i0, c->pipe_h2d, staged[j]);
+        if (s0 != SC_OK) return s0;
+        SC_HIP(c, hipEventRecord(c->pipe_in[j], c->pipe_h2d));
+        SC_HIP(c, hipStreamWaitEvent(c->stream, c->pipe_in[j], 0));
+        SC_HIP(c, enqueue_batch(c, ws, m, c->stream, false));
+        SC_HIP(c, hipEventRecord(c->pipe_done[j], c->stream));
+        c->stats.launches++;
+        c->stats.events += m;
+    }
+    for (uint32_t k = nb >= 2 ? nb - 2 : 0; k < nb; ++k) {
+        const sc_status fs = finish(k);
+        if (fs == SC_ERR_DEVICE) return fs;
+        total = worst(total, fs);
+    }
+    return total;
 }
 
 sc_status sc_process_events_static(sc_ctx* c, const sc_event* ev, uint32_t n, sc_clusters* out,
@@ -1321,7 +1480,7 @@ sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best
     uint64_t tot_cl = 0, tot_adc = 0;
     for (uint32_t i = 0; i < n; ++i) {
         uint64_t span;
-        if (ev[i].mem == SC_MEM_HOST) {
+        if (host_mem(ev[i].mem)) {
             span = event_span(ev[i].fed_offset, c->n_fed);
         } else {
             std::vector<uint64_t> fo(c->n_fed + 1);

@@ -68,6 +68,51 @@ def test_full_detector_per_xcd_order_exact(full, waves, chunk, graph):
         ctx.tuning = before
 
 
+@pytest.mark.parametrize("batch", [1, 3, 8, 24])
+@pytest.mark.parametrize("layout", ["scattered", "packed"])
+def test_pipelined_host_ingest_exact(full, batch, layout):
+    """sc_process_pipelined over 24 events (the 8 full-size events three times) in pageable host,
+    page-locked host and device memory, mixed, with device and host outputs, in batches of
+    `batch` (a ragged last batch for 3). Page-locked events are separate buffers, or back to back
+    in one buffer (then consecutive ones share a transfer). Every event gives the oracle's
+    clusters, and the same bytes as sc_process_events."""
+    cal, evs, refs, ctx = full
+    hosts = [sc.Event(e.zs, e.fed_offset) for e in evs]
+    pinned = [h.to_pinned() for h in hosts] if layout == "scattered" else sc.pack_pinned(hosts)
+    devs = [h.to_device() for h in hosts]
+    kinds = [hosts, pinned, devs]
+    order = [(i % 8, (i // 2) % 3) for i in range(24)]
+    events = [kinds[k][i] for i, k in order]
+    outs = [ctx.output(*sc.safe_caps(hosts[i]), device=(j % 4 != 1))
+            for j, (i, _) in enumerate(order)]
+    rc, sts = ctx.process_pipelined(events, outs, batch)
+    assert rc == sc.SC_OK and sts == [sc.SC_OK] * 24
+    for j, ((i, k), o) in enumerate(zip(order, outs)):
+        compare_clusters(*o.to_numpy()[:2], refs[i], f"pipelined event {j} kind {k}")
+    one = [ctx.output(*sc.safe_caps(hosts[i])) for i in range(8)]
+    ctx.process_events(devs, one)
+    for j, ((i, _), o) in enumerate(zip(order, outs)):
+        a, b = o.to_numpy(), one[i].to_numpy()
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_pipelined_statuses_per_event(full):
+    """An event whose outputs are too small overflows alone; the others of its batch and of the
+    other batches are exact, and a second call on the same context reuses the slots."""
+    cal, evs, refs, ctx = full
+    pinned = sc.pack_pinned([sc.Event(e.zs, e.fed_offset) for e in evs])
+    for rep in range(2):
+        outs = [ctx.output(*sc.safe_caps(p)) for p in pinned]
+        outs[5] = ctx.output(max(1, refs[5].cl.size // 2), refs[5].adc.size)
+        rc, sts = ctx.process_pipelined(pinned, outs, 3)
+        assert rc == sc.SC_ERR_OVERFLOW
+        assert sts == [sc.SC_OK] * 5 + [sc.SC_ERR_OVERFLOW] + [sc.SC_OK] * 2
+        assert outs[5].cs.n_cl == refs[5].cl.size
+        for i in (0, 1, 2, 3, 4, 6, 7):
+            compare_clusters(*outs[i].to_numpy()[:2], refs[i], f"call {rep} event {i}")
+
+
 def test_event_alone_equals_event_in_any_batch(full):
     cal, evs, refs, ctx = full
     pairs = [(e.zs, e.fed_offset) for e in evs]
