@@ -24,8 +24,19 @@ available; these distributions stand in for it):
   * signal: x = gain(apv) * deposit + noise * N(0, 1) on every strip, ADC = clamp(rint(x), 0, 255);
   * the front end keeps a strip in the ZS record when its ADC exceeds twice its noise (FP32).
 
+Synthetic geometry (the paper's next step converts clusters to global hit coordinates; the real
+tracker geometry and cabling are not available, so this layout stands in for them):
+  * modules: each block of 24 consecutive channels of a FED is cut into modules of 2 or 3
+    consecutive channels (512 or 768 strips), sizes drawn at random; a channel's strips start at
+    256 x (its place in the module) in module strip numbering;
+  * placement: barrel-like; a module sits on one of ten layers of radius 25 to 110 cm, at a
+    random azimuth phi and z in [-100, 100] cm; its strips run along z, so the measurement
+    direction is the tangent (-sin phi, cos phi, 0), tilted out of the transverse plane by a
+    random angle in [-0.1, 0.1] rad; pitch 80 um on the four inner layers, 120 um on the next
+    three and 183 um on the outer three.
+
 Random streams: ``numpy.random.Generator(PCG64(SeedSequence([11489, config_id, stream, index])))``
-with stream 0 = calibration, stream 1 = event ``index``.
+with stream 0 = calibration, stream 1 = event ``index``, stream 2 = geometry.
 """
 from __future__ import annotations
 
@@ -47,7 +58,10 @@ __all__ = [
     "CHANNELS_PER_FED", "STRIPS_PER_CHANNEL", "STRIPS_PER_APV", "STRIPS_PER_FED",
     "GenConfig", "CONFIGS", "Calibration", "Event", "make_calibration", "make_event",
     "make_events", "encode_dense", "encode_channel_runs", "assemble_feds", "rng_for",
+    "Geometry", "make_geometry", "MODULE_BLOCK",
 ]
+
+MODULE_BLOCK = 24   # modules never cross a multiple of 24 channels of a FED
 
 
 @dataclasses.dataclass(frozen=True)
@@ -135,6 +149,50 @@ def make_calibration(cfg: GenConfig) -> Calibration:
     gain = rng.normal(cfg.gain_mu, cfg.gain_sigma, size=n // STRIPS_PER_APV).astype(np.float32)
     bad = (rng.random(n) < cfg.p_bad).astype(np.uint8)
     return Calibration(cfg.n_fed, noise, gain, bad)
+
+
+@dataclasses.dataclass
+class Geometry:
+    channel_module: np.ndarray   # uint32 [n_fed*96]: module of each channel
+    channel_first: np.ndarray    # uint32 [n_fed*96]: module strip number of the channel's strip 0
+    module_strips: np.ndarray    # uint32 [n_modules]: 512 or 768
+    origin: np.ndarray           # float32 [n_modules, 3]: module centre, cm
+    u_dir: np.ndarray            # float32 [n_modules, 3]: unit vector across the strips
+    pitch: np.ndarray            # float32 [n_modules]: strip pitch, cm
+
+    @property
+    def n_modules(self) -> int:
+        return int(self.module_strips.size)
+
+
+def make_geometry(cfg: GenConfig) -> Geometry:
+    rng = rng_for(cfg.config_id, 2, 0)
+    sizes = []
+    for _ in range(cfg.n_fed * (CHANNELS_PER_FED // MODULE_BLOCK)):
+        left = MODULE_BLOCK
+        while left:
+            k = left if left in (2, 3) else 2 if left == 4 else int(rng.integers(2, 4))
+            sizes.append(k)
+            left -= k
+    sizes = np.array(sizes, dtype=np.int64)
+    n_mod = sizes.size
+    channel_module = np.repeat(np.arange(n_mod), sizes).astype(np.uint32)
+    starts = np.cumsum(sizes) - sizes
+    channel_first = ((np.arange(channel_module.size) - np.repeat(starts, sizes))
+                     * STRIPS_PER_CHANNEL).astype(np.uint32)
+    radii = np.linspace(25.0, 110.0, 10)
+    pitches = np.array([0.0080] * 4 + [0.0120] * 3 + [0.0183] * 3)
+    layer = rng.integers(0, 10, size=n_mod)
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=n_mod)
+    z = rng.uniform(-100.0, 100.0, size=n_mod)
+    tilt = rng.uniform(-0.1, 0.1, size=n_mod)
+    r = radii[layer]
+    origin = np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1).astype(np.float32)
+    u_dir = np.stack([-np.sin(phi) * np.cos(tilt), np.cos(phi) * np.cos(tilt), np.sin(tilt)],
+                     axis=1).astype(np.float32)
+    return Geometry(channel_module, channel_first,
+                    (sizes * STRIPS_PER_CHANNEL).astype(np.uint32), origin, u_dir,
+                    pitches[layer].astype(np.float32))
 
 
 def _event_occupancy(cfg: GenConfig, rng: np.random.Generator) -> float:
