@@ -270,6 +270,36 @@ sc_status sc_serve_replay(sc_ctx *ctx, const sc_event *ev, uint32_t n_ev, sc_clu
                           uint32_t n_out, uint32_t n, double rate_hz, uint64_t seed,
                           double *latency_us, double *phase_us, double *events_per_s);
 
+/* Module geometry for sc_cluster_hits. Planar modules with parallel strips; a module is read out
+ * by one or more FED channels. All host pointers; sc_set_geometry copies them to the device. */
+typedef struct {
+    uint32_t n_modules;
+    const uint32_t *channel_module; /* [n_fed*96]: module of each FED channel, < n_modules */
+    const uint32_t *channel_first;  /* [n_fed*96]: module strip number of the channel's strip 0;
+                                       channel_first + 256 <= module_strips of its module */
+    const uint32_t *module_strips;  /* [n_modules]: strips across the module, 256..2^20 */
+    const float *origin;            /* [n_modules*3]: module centre x, y, z (cm), finite */
+    const float *u_dir;             /* [n_modules*3]: measurement direction across the strips,
+                                       a unit vector, finite */
+    const float *pitch;             /* [n_modules]: strip pitch (cm), finite and > 0 */
+} sc_geometry;
+
+/* Keep a module geometry resident in the context for sc_cluster_hits (replacing any earlier
+ * one). SC_ERR_INVALID_ARG if a pointer is NULL or an entry is out of range; the context keeps
+ * its previous geometry then. */
+sc_status sc_set_geometry(sc_ctx *ctx, const sc_geometry *geom);
+
+/* Global hit coordinates of clusters, the step after clustering (§5: clusters are converted to
+ * global hits as input for tracking). For a cluster in channel c with barycenter b: position
+ * p = channel_first[c] + b strips from the module's edge, u = (p - module_strips/2) * pitch from
+ * the module centre, hit = origin + u * u_dir (along the strips the hit is taken at the centre).
+ * For each i < n: the first min(out[i].n_cl, out[i].cap_cl) records at out[i].cl (device memory,
+ * out[i].mem == SC_MEM_DEVICE) give hits[i][k] = {x, y, z, u} (FP32, 16 bytes per cluster, device
+ * memory, 16-byte aligned; the caller owns it). A record whose channel is past the detector gets
+ * NaN. One launch for all n events; synchronous. SC_ERR_INVALID_ARG without a geometry, for host
+ * outputs, or for a NULL or misaligned hits[i] with clusters to write. */
+sc_status sc_cluster_hits(sc_ctx *ctx, const sc_clusters *out, uint32_t n, float *const *hits);
+
 /* Tuning of the fused kernel. sc_autotune times every candidate choice on the given events
  * (device or host), checks that all choices give identical clusters, keeps the fastest and, if
  * opt->tune_cache was set, stores it there. */

@@ -36,7 +36,8 @@ CLUSTER_DTYPE = np.dtype([("channel", "<u4"), ("first", "<u2"), ("width", "<u2")
 
 EXPORTED = ["sc_default_options", "sc_create", "sc_destroy", "sc_unpack", "sc_cluster",
             "sc_process_events", "sc_process_pipelined", "sc_process_events_static", "sc_submit", "sc_poll", "sc_serve_replay", "sc_get_tuning",
-            "sc_set_tuning", "sc_autotune", "sc_get_stats", "sc_last_error"]
+            "sc_set_tuning", "sc_autotune", "sc_get_stats", "sc_last_error", "sc_set_geometry",
+            "sc_cluster_hits"]
 
 
 class ScError(RuntimeError):
@@ -67,6 +68,12 @@ class ScClusters(ctypes.Structure):
                 ("adc", ctypes.c_void_p), ("cap_adc", ctypes.c_uint32),
                 ("n_adc", ctypes.c_uint32), ("chan_status", ctypes.c_void_p),
                 ("mem", ctypes.c_int)]
+
+
+class ScGeometry(ctypes.Structure):
+    _fields_ = [("n_modules", ctypes.c_uint32), ("channel_module", ctypes.c_void_p),
+                ("channel_first", ctypes.c_void_p), ("module_strips", ctypes.c_void_p),
+                ("origin", ctypes.c_void_p), ("u_dir", ctypes.c_void_p), ("pitch", ctypes.c_void_p)]
 
 
 class ScTuning(ctypes.Structure):
@@ -124,6 +131,9 @@ def lib():
             "sc_autotune": ([P, ctypes.POINTER(ScEvent), ctypes.c_uint32,
                              ctypes.POINTER(ScTuning)], st),
             "sc_get_stats": ([P, ctypes.POINTER(ScStats)], st),
+            "sc_set_geometry": ([P, ctypes.POINTER(ScGeometry)], st),
+            "sc_cluster_hits": ([P, ctypes.POINTER(ScClusters), ctypes.c_uint32,
+                                 ctypes.POINTER(ctypes.c_void_p)], st),
             "sc_last_error": ([P], ctypes.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -499,6 +509,37 @@ class Context:
         self._order()
         self._check(lib().sc_autotune(self._h, evs, n, ctypes.byref(t)))
         return {f: getattr(t, f) for f, _ in ScTuning._fields_}
+
+    def set_geometry(self, geom):
+        """Module geometry (channel_module, channel_first, module_strips, origin [M, 3], u_dir
+        [M, 3], pitch) for cluster_hits, kept on the device."""
+        arrs = (np.ascontiguousarray(geom.channel_module, np.uint32),
+                np.ascontiguousarray(geom.channel_first, np.uint32),
+                np.ascontiguousarray(geom.module_strips, np.uint32),
+                np.ascontiguousarray(geom.origin, np.float32).reshape(-1),
+                np.ascontiguousarray(geom.u_dir, np.float32).reshape(-1),
+                np.ascontiguousarray(geom.pitch, np.float32))
+        if arrs[0].size != self.n_fed * CHANNELS_PER_FED or arrs[1].size != arrs[0].size:
+            raise ValueError("channel tables must have n_fed * 96 entries")
+        n_mod = arrs[2].size
+        if arrs[3].size != 3 * n_mod or arrs[4].size != 3 * n_mod or arrs[5].size != n_mod:
+            raise ValueError("module tables must have n_modules entries (x3 for vectors)")
+        g = ScGeometry(n_mod, *[a.ctypes.data for a in arrs])
+        self._check(lib().sc_set_geometry(self._h, ctypes.byref(g)))
+
+    def cluster_hits(self, outs, hits=None):
+        """Global hits of the clusters of device outputs: one float32 [n_cl, 4] tensor per output
+        (x, y, z, u in cm), allocated here unless given."""
+        torch = _torch()
+        n = len(outs)
+        if hits is None:
+            hits = [torch.empty((max(1, min(o.cs.n_cl, o.cs.cap_cl)), 4), dtype=torch.float32,
+                                device=self.device) for o in outs]
+        cs = (ScClusters * n)(*[o.cs for o in outs])
+        ptrs = (ctypes.c_void_p * n)(*[h.data_ptr() for h in hits])
+        self._order()
+        self._check(lib().sc_cluster_hits(self._h, cs, n, ptrs))
+        return [h[:min(o.cs.n_cl, o.cs.cap_cl)] for h, o in zip(hits, outs)]
 
     def stats(self) -> dict:
         s = ScStats()

@@ -38,11 +38,13 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     k_obj = os.path.join(BUILD, "sc_kernels.o")
+    h_obj = os.path.join(BUILD, "sc_hits.o")
     r_obj = os.path.join(BUILD, "sc_runtime.o")
     _run(["hipcc", *DEVICE_FLAGS, "-c", os.path.join(CSRC, "sc_kernels.hip"), "-o", k_obj])
+    _run(["hipcc", *DEVICE_FLAGS, "-c", os.path.join(CSRC, "sc_hits.hip"), "-o", h_obj])
     _run(["hipcc", *HOST_FLAGS, "-c", os.path.join(CSRC, "sc_runtime.cpp"), "-o", r_obj])
     tmp = LIB + ".tmp"
-    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, k_obj, r_obj,
+    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, k_obj, h_obj, r_obj,
           "-lpthread"])
     os.replace(tmp, LIB)
     if verbose:

@@ -80,6 +80,18 @@ hipError_t launch_cluster_dense(const uint8_t* adc_dense, const FusedArgs& a,
 hipError_t launch_unpack(const uint8_t* zs, const uint64_t* fed_off, uint32_t n_fed,
                          uint8_t* adc_dense, uint8_t* chan_status, EventResult* res,
                          hipStream_t stream);
+// Cluster -> global hit conversion: per event, its records, their count and its hit output.
+struct HitDesc {
+    const sc_cluster_rec* cl;
+    float* hits;   // 4 floats per cluster
+    uint32_t n;
+    uint32_t pad;
+};
+// chan: [n_channels] {module, first module strip}; mod: [2 * n_modules] float4 {origin, pitch},
+// {u_dir, module_strips / 2}.
+hipError_t launch_hits(const HitDesc* d, uint32_t n_ev, uint32_t max_n, const uint32_t* chan,
+                       const float* mod, uint32_t n_channels, hipStream_t stream);
+
 // Resident workgroups per compute unit for a tile shape (waves per tile, digis per chunk).
 int fused_blocks_per_cu(uint32_t tile_waves, uint32_t chunk_digis, bool dense);
 bool tile_shape_supported(uint32_t tile_waves, uint32_t chunk_digis);

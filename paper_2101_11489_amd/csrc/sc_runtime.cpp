@@ -174,6 +174,10 @@ struct sc_ctx {
     // sc_process_pipelined: two staging slots, a stream for the transfers to the device and one
     // for host outputs coming back (made on first use)
     Workspace pipe_ws[2];
+    // sc_cluster_hits: the resident geometry tables and the per-event descriptors
+    DevBuf geo_chan, geo_mod, hit_desc;
+    PinBuf h_hit_desc;
+    uint32_t geo_modules = 0;
     hipStream_t pipe_h2d = nullptr, pipe_d2h = nullptr;
     hipEvent_t pipe_in[2] = {nullptr, nullptr}, pipe_done[2] = {nullptr, nullptr};
 };
@@ -1043,6 +1047,10 @@ void sc_destroy(sc_ctx* c) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->ws.release();
     c->h_static.release();
+    c->geo_chan.release();
+    c->geo_mod.release();
+    c->hit_desc.release();
+    c->h_hit_desc.release();
     if (c->pipe_h2d) (void)hipStreamSynchronize(c->pipe_h2d);
     for (int j = 0; j < 2; ++j) {
         c->pipe_ws[j].release();
@@ -1177,6 +1185,92 @@ sc_status sc_process_events(sc_ctx* c, const sc_event* ev, uint32_t n, sc_cluste
     }
     SC_HIP(c, hipSetDevice(c->device));
     return run_batch(c, ev, n, out, ev_status, all_device);
+}
+
+sc_status sc_set_geometry(sc_ctx* c, const sc_geometry* g) {
+    if (!c) return SC_ERR_INVALID_ARG;
+    if (c->poisoned) return SC_ERR_DEVICE;
+    if (!g || !g->channel_module || !g->channel_first || !g->module_strips || !g->origin ||
+        !g->u_dir || !g->pitch || g->n_modules == 0)
+        return fail(c, SC_ERR_INVALID_ARG, "sc_set_geometry: NULL table or no modules");
+    const uint32_t n_ch = c->n_fed * kChannelsPerFed;
+    std::vector<uint32_t> chan(2 * (size_t)n_ch);
+    for (uint32_t i = 0; i < n_ch; ++i) {
+        const uint32_t m = g->channel_module[i];
+        if (m >= g->n_modules)
+            return fail(c, SC_ERR_INVALID_ARG, "sc_set_geometry: channel_module out of range");
+        if ((uint64_t)g->channel_first[i] + kStripsPerChannel > g->module_strips[m])
+            return fail(c, SC_ERR_INVALID_ARG,
+                        "sc_set_geometry: channel_first + 256 exceeds module_strips");
+        chan[2 * i] = m;
+        chan[2 * i + 1] = g->channel_first[i];
+    }
+    std::vector<float> mod(8 * (size_t)g->n_modules);
+    for (uint32_t m = 0; m < g->n_modules; ++m) {
+        const float* o = g->origin + 3 * (size_t)m;
+        const float* d = g->u_dir + 3 * (size_t)m;
+        const float pitch = g->pitch[m];
+        const uint32_t strips = g->module_strips[m];
+        bool ok = std::isfinite(pitch) && pitch > 0.0f && strips >= (uint32_t)kStripsPerChannel &&
+                  strips <= (1u << 20);
+        for (int k = 0; k < 3; ++k) ok = ok && std::isfinite(o[k]) && std::isfinite(d[k]);
+        if (!ok) return fail(c, SC_ERR_INVALID_ARG, "sc_set_geometry: module entry out of range");
+        float* a = mod.data() + 8 * (size_t)m;
+        a[0] = o[0], a[1] = o[1], a[2] = o[2], a[3] = pitch;
+        a[4] = d[0], a[5] = d[1], a[6] = d[2], a[7] = 0.5f * (float)strips;
+    }
+    SC_HIP(c, hipSetDevice(c->device));
+    SC_HIP(c, c->geo_chan.ensure(sizeof(uint32_t) * chan.size()));
+    SC_HIP(c, c->geo_mod.ensure(sizeof(float) * mod.size()));
+    SC_HIP(c, hipMemcpyAsync(c->geo_chan.p, chan.data(), sizeof(uint32_t) * chan.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    SC_HIP(c, hipMemcpyAsync(c->geo_mod.p, mod.data(), sizeof(float) * mod.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    SC_HIP(c, hipStreamSynchronize(c->stream));
+    c->geo_modules = g->n_modules;
+    return SC_OK;
+}
+
+sc_status sc_cluster_hits(sc_ctx* c, const sc_clusters* out, uint32_t n, float* const* hits) {
+    if (!c) return SC_ERR_INVALID_ARG;
+    if (c->poisoned) return SC_ERR_DEVICE;
+    if (!c->geo_modules) return fail(c, SC_ERR_INVALID_ARG, "sc_cluster_hits: no geometry set");
+    if (!out || !hits || n == 0) return fail(c, SC_ERR_INVALID_ARG, "NULL argument or n == 0");
+    SC_HIP(c, hipSetDevice(c->device));
+    // one launch covers at most 65535 events (the grid's y extent): larger n goes in pieces
+    constexpr uint32_t kMaxY = 65535;
+    SC_HIP(c, c->hit_desc.ensure(sizeof(HitDesc) * std::min(n, kMaxY)));
+    SC_HIP(c, c->h_hit_desc.ensure(sizeof(HitDesc) * std::min(n, kMaxY)));
+    for (uint32_t i = 0; i < n; ++i) {
+        if (out[i].mem != SC_MEM_DEVICE)
+            return fail(c, SC_ERR_INVALID_ARG, "sc_cluster_hits: clusters must be in device memory");
+        const uint32_t k = std::min(out[i].n_cl, out[i].cap_cl);
+        if (k && (!out[i].cl || !hits[i] || (reinterpret_cast<uintptr_t>(hits[i]) & 15u) ||
+                  (reinterpret_cast<uintptr_t>(out[i].cl) & 15u)))
+            return fail(c, SC_ERR_INVALID_ARG,
+                        "sc_cluster_hits: NULL or misaligned clusters or hits buffer");
+    }
+    for (uint32_t i0 = 0; i0 < n; i0 += kMaxY) {
+        const uint32_t m = std::min(kMaxY, n - i0);
+        HitDesc* hd = c->h_hit_desc.as<HitDesc>();
+        uint32_t max_n = 0;
+        for (uint32_t i = 0; i < m; ++i) {
+            const sc_clusters& o = out[i0 + i];
+            const uint32_t k = std::min(o.n_cl, o.cap_cl);
+            hd[i] = HitDesc{o.cl, hits[i0 + i], k, 0u};
+            max_n = std::max(max_n, k);
+        }
+        SC_HIP(c, hipMemcpyAsync(c->hit_desc.p, hd, sizeof(HitDesc) * m, hipMemcpyHostToDevice,
+                                 c->stream));
+        SC_HIP(c, hipEventRecord(c->ev0, c->stream));
+        SC_HIP(c, launch_hits(c->hit_desc.as<HitDesc>(), m, max_n, c->geo_chan.as<uint32_t>(),
+                              c->geo_mod.as<float>(), c->n_fed * kChannelsPerFed, c->stream));
+        SC_HIP(c, hipEventRecord(c->ev1, c->stream));
+        // the descriptors' pinned copy is rewritten by the next piece: finish this one first
+        SC_HIP(c, hipStreamSynchronize(c->stream));
+        record_kernel_ms(c);
+    }
+    return SC_OK;
 }
 
 sc_status sc_process_pipelined(sc_ctx* c, const sc_event* ev, uint32_t n, sc_clusters* out,
