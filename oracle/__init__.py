@@ -59,6 +59,9 @@ def lib():
         L.oracle_cluster.restype = ctypes.c_int
         L.oracle_process_event.argtypes = [P, P, u32, P, P, P, f32, f32, f32, P, P, P, u64, P,
                                            u64, P, P]
+        L.oracle_cluster_modules.argtypes = [P, u32, P, P, P, f32, f32, f32, P, P, u64, P, u64,
+                                             P, P]
+        L.oracle_cluster_modules.restype = ctypes.c_int
         L.oracle_process_event.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -102,7 +105,12 @@ def flags(adc, noise, gain, bad, t_seed=T_SEED, t_channel=T_CHANNEL):
 
 
 def cluster(adc, noise, gain, bad, t_seed=T_SEED, t_channel=T_CHANNEL, t_cluster=T_CLUSTER,
-            cap_cl=None, cap_adc=None) -> Clusters:
+            cap_cl=None, cap_adc=None, joins=None) -> Clusters:
+    """Three-threshold clustering of dense ADCs; with joins (u8 per channel, nonzero: the channel
+    reads the same module as the previous channel of its FED) the module-aware variant."""
+    if joins is not None:
+        return _cluster_modules(adc, noise, gain, bad, t_seed, t_channel, t_cluster, cap_cl,
+                                cap_adc, joins)
     adc = np.ascontiguousarray(adc, dtype=np.uint8)
     n_fed = adc.size // (96 * 256)
     assert adc.size == n_fed * 96 * 256
@@ -124,10 +132,36 @@ def cluster(adc, noise, gain, bad, t_seed=T_SEED, t_channel=T_CHANNEL, t_cluster
     return Clusters(cl[:min(ncl, n_cl.value)], out_adc[:min(nadc, n_adc.value)], int(rc))
 
 
+def _cluster_modules(adc, noise, gain, bad, t_seed, t_channel, t_cluster, cap_cl, cap_adc,
+                     joins) -> Clusters:
+    adc = np.ascontiguousarray(adc, dtype=np.uint8)
+    n_fed = adc.size // (96 * 256)
+    assert adc.size == n_fed * 96 * 256
+    noise = np.ascontiguousarray(noise, np.float32)
+    gain = np.ascontiguousarray(gain, np.float32)
+    bad = np.ascontiguousarray(bad, np.uint8)
+    joins = np.ascontiguousarray(joins, np.uint8)
+    assert joins.size == n_fed * 96
+    n_cl = ctypes.c_uint64()
+    n_adc = ctypes.c_uint64()
+    L = lib()
+    L.oracle_cluster_modules(_p(adc), n_fed, _p(noise), _p(gain), _p(bad), t_seed, t_channel,
+                             t_cluster, _p(joins), None, 0, None, 0, ctypes.byref(n_cl),
+                             ctypes.byref(n_adc))
+    ncl = n_cl.value if cap_cl is None else cap_cl
+    nadc = n_adc.value if cap_adc is None else cap_adc
+    cl = np.zeros(max(ncl, 1), dtype=CLUSTER_DTYPE)
+    out_adc = np.zeros(max(nadc, 1), dtype=np.uint16)
+    rc = L.oracle_cluster_modules(_p(adc), n_fed, _p(noise), _p(gain), _p(bad), t_seed,
+                                  t_channel, t_cluster, _p(joins), _p(cl), ncl, _p(out_adc), nadc,
+                                  ctypes.byref(n_cl), ctypes.byref(n_adc))
+    return Clusters(cl[:min(ncl, n_cl.value)], out_adc[:min(nadc, n_adc.value)], int(rc))
+
+
 def process_event(zs, fed_offset, noise, gain, bad, t_seed=T_SEED, t_channel=T_CHANNEL,
-                  t_cluster=T_CLUSTER) -> Clusters:
+                  t_cluster=T_CLUSTER, joins=None) -> Clusters:
     adc, st, rc = unpack(zs, fed_offset)
-    out = cluster(adc, noise, gain, bad, t_seed, t_channel, t_cluster)
+    out = cluster(adc, noise, gain, bad, t_seed, t_channel, t_cluster, joins=joins)
     out.status = rc
     out.chan_status = st
     return out

@@ -201,6 +201,89 @@ int oracle_cluster(const uint8_t *adc, uint32_t n_fed, const float *noise, const
     return (ncl > cap_cl || nadc > cap_adc) ? -2 : 0;
 }
 
+/* ------------------------------------------------------------------------------------------ */
+/* Module-aware clustering. The channel map of §2 records each channel's location; a detector  */
+/* module is read out by several channels of one FED. Reading used here:                       */
+/*  M1 joins[c] != 0 says channel c reads the same module as channel c-1 of the same FED (it    */
+/*     is ignored on a FED's first channel); consecutive joined channels form one strip row,   */
+/*     strip s of its k-th channel at row position 256 k + s;                                  */
+/*  M2 R1-R3 per strip as before; R4 with "inside one channel" replaced by "inside one row": a  */
+/*     run goes on from strip 255 of a channel to strip 0 of the next channel of its row;      */
+/*  M3 R5 over the run in row order; R6 with the record's channel and first strip those of the */
+/*     run's first strip, width counted along the row (up to 256 times the row's channels),   */
+/*     each member's gain that of its own APV, and the barycenter in strip units from strip 0  */
+/*     of the record's channel (so past 256 when the cluster goes on into the next channel);   */
+/*  M4 R7 unchanged. With no joins this is R1-R7 exactly.                                      */
+/* ------------------------------------------------------------------------------------------ */
+int oracle_cluster_modules(const uint8_t *adc, uint32_t n_fed, const float *noise,
+                           const float *gain, const uint8_t *bad, float t_seed, float t_channel,
+                           float t_cluster, const uint8_t *joins, oracle_cluster_t *cl,
+                           uint64_t cap_cl, uint16_t *adc_out, uint64_t cap_adc, uint64_t *n_cl,
+                           uint64_t *n_adc)
+{
+    uint64_t n_ch = (uint64_t)n_fed * NCH, c0 = 0;
+    uint64_t ncl = 0, nadc = 0;
+    uint8_t act[NCH * NSTRIP], seed[NCH * NSTRIP];
+    while (c0 < n_ch) {
+        /* the row: c0 and the channels joined to it, inside one FED */
+        uint64_t c1 = c0 + 1, base = c0 * NSTRIP, len, k;
+        while (c1 < n_ch && c1 % NCH != 0 && joins[c1]) ++c1;
+        len = (c1 - c0) * NSTRIP;
+        for (k = 0; k < len; ++k) {
+            uint64_t gi = base + k;
+            float af = (float)adc[gi];
+            float gs = gain[gi / NAPV];
+            act[k] = (uint8_t)(!strip_unusable(noise[gi], gs, bad[gi]) &&
+                               af > t_channel * noise[gi]);
+            seed[k] = (uint8_t)(act[k] && af > t_seed * noise[gi]);
+        }
+        k = 0;
+        while (k < len) {
+            uint64_t l, r, i, has_seed = 0, q_raw = 0;
+            float sum_n2 = 0.0f;
+            if (!act[k]) { ++k; continue; }
+            l = k;
+            while (k < len && act[k]) ++k;
+            r = k - 1;
+            for (i = l; i <= r; ++i) {
+                has_seed |= seed[i];
+                q_raw += adc[base + i];
+                sum_n2 = fmaf(noise[base + i], noise[base + i], sum_n2);
+            }
+            if (!has_seed) continue;
+            if (!((float)q_raw >= t_cluster * sqrtf(sum_n2))) continue;
+            {
+                uint64_t ch_off = (l / NSTRIP) * NSTRIP;   /* row position of the record's strip 0 */
+                uint32_t width = (uint32_t)(r - l + 1), charge = 0;
+                double num = 0.0, den = 0.0;
+                for (i = l; i <= r; ++i) {
+                    float q = rintf((float)adc[base + i] / gain[(base + i) / NAPV]);
+                    uint16_t cq = q > 65535.0f ? (uint16_t)65535 : (uint16_t)q;
+                    charge += cq;
+                    num += ((double)(i - ch_off) + 0.5) * (double)cq;
+                    den += (double)cq;
+                    if (nadc < cap_adc) adc_out[nadc] = cq;
+                    ++nadc;
+                }
+                if (ncl < cap_cl) {
+                    oracle_cluster_t *o = &cl[ncl];
+                    o->channel = (uint32_t)(c0 + l / NSTRIP);
+                    o->first = (uint16_t)(l % NSTRIP);
+                    o->width = (uint16_t)width;
+                    o->charge = charge;
+                    o->barycenter = den > 0.0 ? (float)(num / den)
+                                              : (float)(l % NSTRIP) + (float)width * 0.5f;
+                }
+                ++ncl;
+            }
+        }
+        c0 = c1;
+    }
+    *n_cl = ncl;
+    *n_adc = nadc;
+    return (ncl > cap_cl || nadc > cap_adc) ? -2 : 0;
+}
+
 int oracle_process_event(const uint8_t *zs, const uint64_t *fed_offset, uint32_t n_fed,
                          const float *noise, const float *gain, const uint8_t *bad,
                          float t_seed, float t_channel, float t_cluster,

@@ -33,7 +33,7 @@ enum { ORACLE_CH_MALFORMED = 1, ORACLE_FED_TRAILING = 2 };
 typedef struct {
     uint32_t channel;   /* global channel index fed*96 + ch */
     uint16_t first;     /* first strip of the cluster in its channel, 0..255 */
-    uint16_t width;     /* number of strips, 1..256 */
+    uint16_t width;     /* number of strips, 1..256 (up to 256 per channel of a module row) */
     uint32_t charge;    /* sum of gain-corrected ADCs */
     float barycenter;   /* charge-weighted strip centre, channel-local; strip s spans [s, s+1) */
 } oracle_cluster_t;
@@ -60,6 +60,16 @@ int oracle_cluster(const uint8_t *adc, uint32_t n_fed, const float *noise, const
                    const uint8_t *bad, float t_seed, float t_channel, float t_cluster,
                    oracle_cluster_t *cl, uint64_t cap_cl, uint16_t *adc_out, uint64_t cap_adc,
                    uint64_t *n_cl, uint64_t *n_adc);
+
+/* Module-aware clustering (readings M1-M4 in oracle.c): as oracle_cluster, except that a run
+ * goes on across the edge into channel c when joins[c] != 0 (n_fed*96 bytes; channel c reads the
+ * same module as channel c-1 of its FED). Records keep the first strip's channel; the width may
+ * pass 256 and the barycenter counts from strip 0 of the record's channel. */
+int oracle_cluster_modules(const uint8_t *adc, uint32_t n_fed, const float *noise,
+                           const float *gain, const uint8_t *bad, float t_seed, float t_channel,
+                           float t_cluster, const uint8_t *joins, oracle_cluster_t *cl,
+                           uint64_t cap_cl, uint16_t *adc_out, uint64_t cap_adc, uint64_t *n_cl,
+                           uint64_t *n_adc);
 
 /* Unpack then cluster one event. scratch_adc: n_fed*96*256 bytes of caller memory.
  * Returns -2 on output overflow, else the unpack status (0 or 1). */

@@ -50,19 +50,47 @@ MUTANTS = {
 }
 
 
-@pytest.mark.parametrize("name", sorted(MUTANTS))
+# Planted mistakes in the module-aware function (readings M1-M4), killed by its own pins.
+MODULE_MUTANTS = {
+    "rows_ignore_joins": ("while (c1 < n_ch && c1 % NCH != 0 && joins[c1]) ++c1;",
+                          "while (0) ++c1;"),
+    "rows_cross_feds": ("while (c1 < n_ch && c1 % NCH != 0 && joins[c1]) ++c1;",
+                        "while (c1 < n_ch && joins[c1]) ++c1;"),
+    "bary_from_row_start": ("num += ((double)(i - ch_off) + 0.5) * (double)cq;",
+                            "num += ((double)i + 0.5) * (double)cq;"),
+    "record_channel_row_start": ("o->channel = (uint32_t)(c0 + l / NSTRIP);",
+                                 "o->channel = (uint32_t)c0;"),
+    "first_in_row_numbering": ("o->first = (uint16_t)(l % NSTRIP);", "o->first = (uint16_t)l;"),
+    "gain_of_row_start": ("float q = rintf((float)adc[base + i] / gain[(base + i) / NAPV]);",
+                          "float q = rintf((float)adc[base + i] / gain[(base + l) / NAPV]);"),
+}
+MARK = "/* Module-aware clustering."
+
+
+def _mutate(src, old, new, module):
+    """Applies the mutation inside the plain functions (before MARK) or inside the module-aware
+    one (after it); the site must be unique there."""
+    head, tail = src.split(MARK, 1)
+    part = tail if module else head
+    assert part.count(old) == 1, f"mutation site not unique/found: {old!r}"
+    part = part.replace(old, new)
+    return (head + MARK + part) if module else (part + MARK + tail)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS) + sorted(MODULE_MUTANTS))
 def test_mutant_is_killed(name, tmp_path):
-    old, new = MUTANTS[name]
+    module = name in MODULE_MUTANTS
+    old, new = (MODULE_MUTANTS if module else MUTANTS)[name]
     src = open(oracle.SRC).read()
-    assert src.count(old) == 1, f"mutation site not unique/found: {old!r}"
     msrc = tmp_path / "oracle_mutant.c"
-    msrc.write_text(src.replace(old, new))
+    msrc.write_text(_mutate(src, old, new, module))
     lib = str(tmp_path / "liboracle_mutant.so")
     oracle.build(force=True, src=str(msrc), out=lib)
     env = dict(os.environ, ORACLE_LIB=lib, PYTHONDONTWRITEBYTECODE="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         "-m", "not gpu",
-                        os.path.join(HERE, "test_oracle_unpack.py"),
-                        os.path.join(HERE, "test_oracle_cluster.py")],
+                        *([os.path.join(HERE, "test_oracle_modules.py")] if module else
+                          [os.path.join(HERE, "test_oracle_unpack.py"),
+                           os.path.join(HERE, "test_oracle_cluster.py")])],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived every pin:\n{r.stdout[-2000:]}"
