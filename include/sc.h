@@ -122,11 +122,12 @@ typedef struct {
 
 /* One cluster, 16 bytes. */
 typedef struct {
-    uint32_t channel;   /* fed*96 + ch */
+    uint32_t channel;   /* fed*96 + ch: the channel of its first strip */
     uint16_t first;     /* first strip, 0..255 */
-    uint16_t width;     /* strips, 1..256 */
+    uint16_t width;     /* strips, 1..256 (up to 768 with module rows, sc_set_modules) */
     uint32_t charge;    /* sum of gain-corrected member ADCs */
-    float barycenter;   /* channel-local; strip s spans [s, s+1) */
+    float barycenter;   /* from strip 0 of `channel`; strip s spans [s, s+1) (past 256 when a
+                           module-row cluster goes on into the next channel) */
 } sc_cluster_rec;
 
 /* Cluster output of one event. cl/adc/chan_status lie in memory kind mem; n_cl/n_adc are host
@@ -269,6 +270,18 @@ sc_status sc_poll(sc_ctx *ctx, uint64_t ticket, int64_t timeout_us);
 sc_status sc_serve_replay(sc_ctx *ctx, const sc_event *ev, uint32_t n_ev, sc_clusters *out,
                           uint32_t n_out, uint32_t n, double rate_hz, uint64_t seed,
                           double *latency_us, double *phase_us, double *events_per_s);
+
+/* Module-aware clustering (§2: the channel map holds each channel's location and attributes;
+ * here, the detector module a channel reads). channel_module[n_fed*96] names the module of every
+ * FED channel; consecutive channels of one FED with the same module form a row whose strips run
+ * on across the channel edges, so a run of active strips continues from strip 255 of a channel
+ * to strip 0 of the next one of its row, and the cluster keeps the channel and strip where it
+ * starts (thresholds, charge and gains otherwise as before). NULL turns rows off (clusters stop
+ * at every channel edge, the default). Limits of this implementation, SC_ERR_INVALID_ARG beyond
+ * them: a row has at most 3 channels and does not cross a multiple of 24 channels of its FED, and
+ * the tile shape must hold a row (not tile_waves 4 with chunk_digis 2048). Applies to every later
+ * call; not while calls or served events are in flight on the context. */
+sc_status sc_set_modules(sc_ctx *ctx, const uint32_t *channel_module);
 
 /* Module geometry for sc_cluster_hits. Planar modules with parallel strips; a module is read out
  * by one or more FED channels. All host pointers; sc_set_geometry copies them to the device. */

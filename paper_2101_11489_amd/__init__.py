@@ -37,7 +37,7 @@ CLUSTER_DTYPE = np.dtype([("channel", "<u4"), ("first", "<u2"), ("width", "<u2")
 EXPORTED = ["sc_default_options", "sc_create", "sc_destroy", "sc_unpack", "sc_cluster",
             "sc_process_events", "sc_process_pipelined", "sc_process_events_static", "sc_submit", "sc_poll", "sc_serve_replay", "sc_get_tuning",
             "sc_set_tuning", "sc_autotune", "sc_get_stats", "sc_last_error", "sc_set_geometry",
-            "sc_cluster_hits"]
+            "sc_cluster_hits", "sc_set_modules"]
 
 
 class ScError(RuntimeError):
@@ -132,6 +132,7 @@ def lib():
                              ctypes.POINTER(ScTuning)], st),
             "sc_get_stats": ([P, ctypes.POINTER(ScStats)], st),
             "sc_set_geometry": ([P, ctypes.POINTER(ScGeometry)], st),
+            "sc_set_modules": ([P, ctypes.c_void_p], st),
             "sc_cluster_hits": ([P, ctypes.POINTER(ScClusters), ctypes.c_uint32,
                                  ctypes.POINTER(ctypes.c_void_p)], st),
             "sc_last_error": ([P], ctypes.c_char_p),
@@ -509,6 +510,17 @@ class Context:
         self._order()
         self._check(lib().sc_autotune(self._h, evs, n, ctypes.byref(t)))
         return {f: getattr(t, f) for f, _ in ScTuning._fields_}
+
+    def set_modules(self, channel_module):
+        """Module rows from the module of every FED channel (uint32 [n_fed * 96]); None turns
+        them off."""
+        if channel_module is None:
+            self._check(lib().sc_set_modules(self._h, None))
+            return
+        cm = np.ascontiguousarray(channel_module, np.uint32)
+        if cm.size != self.n_fed * CHANNELS_PER_FED:
+            raise ValueError("channel_module must have n_fed * 96 entries")
+        self._check(lib().sc_set_modules(self._h, cm.ctypes.data))
 
     def set_geometry(self, geom):
         """Module geometry (channel_module, channel_first, module_strips, origin [M, 3], u_dir

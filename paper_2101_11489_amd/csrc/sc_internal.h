@@ -37,6 +37,8 @@ struct EventResult {
 struct DeviceCalib {
     const float* noise;   // per strip: noise, or +inf when the strip is unusable
     const float* gain;    // per APV
+    const uint32_t* joins;   // module rows: [n_fed * 4] words, bit c of word c / 32 of FED f set
+                             // when channel c reads the same module as channel c - 1; NULL: none
     uint32_t n_fed;
     float t_seed, t_channel, t_cluster;
 };
@@ -93,7 +95,9 @@ hipError_t launch_hits(const HitDesc* d, uint32_t n_ev, uint32_t max_n, const ui
                        const float* mod, uint32_t n_channels, hipStream_t stream);
 
 // Resident workgroups per compute unit for a tile shape (waves per tile, digis per chunk).
-int fused_blocks_per_cu(uint32_t tile_waves, uint32_t chunk_digis, bool dense);
+int fused_blocks_per_cu(uint32_t tile_waves, uint32_t chunk_digis, bool dense, bool modules);
 bool tile_shape_supported(uint32_t tile_waves, uint32_t chunk_digis);
+// Whether a shape's wave lists hold a module row (768 digis): needed while modules are set.
+bool tile_shape_supports_modules(uint32_t tile_waves, uint32_t chunk_digis);
 
 }  // namespace sc

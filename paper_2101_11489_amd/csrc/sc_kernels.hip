@@ -122,6 +122,26 @@ __device__ __forceinline__ void run_sums(A& a, B& b, uint32_t r) {
     run_sum_step<0x143, 0xc>(a, b, l >= 32u && r + 32u > l);
 }
 
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ void run_sum_step3(uint32_t& a, uint32_t& b, uint32_t& c, bool t) {
+    const uint32_t ya = dpp_in<Ctrl, RowMask>(a), yb = dpp_in<Ctrl, RowMask>(b);
+    const uint32_t yc = dpp_in<Ctrl, RowMask>(c);
+    add_if(a, ya, t);
+    add_if(b, yb, t);
+    add_if(c, yc, t);
+}
+
+// run_sums over three integer values
+__device__ __forceinline__ void run_sums3(uint32_t& a, uint32_t& b, uint32_t& c, uint32_t r) {
+    const uint32_t l = lane(), lr = l & 15u;
+    run_sum_step3<0x111, 0xf>(a, b, c, r >= 1u);
+    run_sum_step3<0x112, 0xf>(a, b, c, r >= 2u);
+    run_sum_step3<0x114, 0xf>(a, b, c, r >= 4u);
+    run_sum_step3<0x118, 0xf>(a, b, c, r >= 8u);
+    run_sum_step3<0x142, 0xa>(a, b, c, (l & 16u) != 0u && r > lr);
+    run_sum_step3<0x143, 0xc>(a, b, c, l >= 32u && r + 32u > l);
+}
+
 // Inclusive sum over the wavefront in six DPP steps: row_shr 1, 2, 4, 8 inside rows of 16 lanes,
 // then row_bcast:15 into rows 1 and 3 and row_bcast:31 into rows 2 and 3.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
@@ -178,6 +198,22 @@ __device__ __forceinline__ uint32_t d_adc(uint32_t d) { return d & 255u; }
 __device__ __forceinline__ uint32_t d_strip(uint32_t d) { return (d >> 8) & 255u; }
 __device__ __forceinline__ uint32_t d_ch(uint32_t d) { return (d >> 16) & 127u; }
 __device__ __forceinline__ uint32_t d_pos(uint32_t d) { return (d >> 8) & 0x7fffu; }
+
+// Module rows (tiles instantiated with kMod): bit c of the FED's join words is set when channel c
+// reads the same module as channel c - 1, whose strips then continue into it (strip 255 of c - 1
+// is followed by strip 0 of c; positions ch * 256 + strip stay consecutive across the edge).
+// A row has at most 3 channels (768 strips) and never crosses a multiple of 24 channels, so the
+// wave groups and the chunks of a group hold whole rows.
+struct Joins {
+    uint32_t w0, w1, w2;
+};
+__device__ __forceinline__ bool joined(const Joins& J, uint32_t ch) {
+    const uint32_t w = ch < 32u ? J.w0 : ch < 64u ? J.w1 : J.w2;
+    return ((w >> (ch & 31u)) & 1u) != 0u;
+}
+// Raw ADC sum | seed count << kQShift in one word: a channel run's sum fits 16 bits (256 x 255),
+// a module row's needs 18 (768 x 255).
+template <bool kMod> constexpr uint32_t kQShift = kMod ? 18u : 16u;
 
 // The little-endian u16 at byte o of a 4-byte aligned LDS buffer, from the two aligned words
 // around it (one ds_read2): LDS reads at odd addresses stall. The caller keeps o + 1 inside the
@@ -395,9 +431,9 @@ __device__ __forceinline__ uint32_t check_channel(TileSmem<W, DW>& sm, P src, ui
 
 // The channel group [c_lo, c_hi) of wave w: digi counts -> offsets in the group (ch_base) and
 // its split into chunks of at most DW digis; returns the number of chunks. Wave-local.
-template <int W, int DW, class CountFn>
+template <bool kMod, int W, int DW, class CountFn>
 __device__ uint32_t plan_chunks(TileSmem<W, DW>& sm, uint32_t w, uint32_t c_lo, uint32_t c_hi,
-                                CountFn count, uint32_t& total) {
+                                const Joins& J, CountFn count, uint32_t& total) {
     uint32_t carry = 0;
     for (uint32_t base = c_lo; base < c_hi; base += kWave) {
         const uint32_t ch = base + lane();
@@ -421,10 +457,24 @@ __device__ uint32_t plan_chunks(TileSmem<W, DW>& sm, uint32_t w, uint32_t c_lo, 
         cf[0] = (uint8_t)c_lo;
         while (c < c_hi) {
             const uint32_t start = uni(sm.ch_base[c + w]);
-            uint32_t c1 = c + 1;   // one channel holds <= 256 <= DW digis
-            while (c1 < c_hi && uni(sm.ch_base[c1 + 1 + w]) - start <= (uint32_t)DW) ++c1;
-            cf[++n] = (uint8_t)c1;
-            c = c1;
+            if constexpr (kMod) {
+                // whole rows only: a row holds <= 768 <= DW digis (the host keeps DW >= 768)
+                uint32_t c1 = c + 1;
+                while (c1 < c_hi && joined(J, c1)) ++c1;
+                while (c1 < c_hi) {
+                    uint32_t c2 = c1 + 1;
+                    while (c2 < c_hi && joined(J, c2)) ++c2;
+                    if (uni(sm.ch_base[c2 + w]) - start > (uint32_t)DW) break;
+                    c1 = c2;
+                }
+                cf[++n] = (uint8_t)c1;
+                c = c1;
+            } else {
+                uint32_t c1 = c + 1;   // one channel holds <= 256 <= DW digis
+                while (c1 < c_hi && uni(sm.ch_base[c1 + 1 + w]) - start <= (uint32_t)DW) ++c1;
+                cf[++n] = (uint8_t)c1;
+                c = c1;
+            }
         }
         n_chunks = n;
     }
@@ -573,15 +623,18 @@ struct OpenRun {
 // Cluster threshold of the runs ending at their lanes (§2: charge against the cluster
 // threshold): accepted when seeded and (float)Q >= t * sqrtf(S), S summed by fmaf from the run's
 // first strip. St, the same sum taken in tree order by run_sums, is within (L + 35) roundings of
-// the exact sum, as the sequential one is within L (L = rp + 1 strips; every path through the
-// tree has at most 35 additions and products for a run of at most 256 strips). So wherever
-// q >= r (1 + e) or q < r (1 - e), with r = t * sqrt(St) and e = (L + 64) * 2^-24, the
+// the exact sum for a run of at most 256 strips, and within (L + 70) for a module row's run of at
+// most 768 (a path through the tree has at most about 10 roundings per 128-digi step, and such
+// runs span at most 3 and 7 steps); the sequential sum is within L (L = rp + 1 strips). Half of
+// that in the square root plus the roundings of the root and the product stay below
+// e = (L + 64) * 2^-24, so wherever q >= r (1 + e) or q < r (1 - e), r = t * sqrt(St), the
 // sequential sum decides the same way. Returns the head bit: kAccBit (accepted), kRedoBit (too
 // close to call: settle_runs decides from the sequential sum) or 0.
+template <bool kMod>
 __device__ __forceinline__ uint32_t cluster_mark(bool end, uint32_t rp, uint32_t Q, float St,
                                                  float t) {
-    const bool seeded = end && (Q >> 16) != 0u;
-    const float q = (float)(Q & 0xffffu);
+    const bool seeded = end && (Q >> kQShift<kMod>) != 0u;
+    const float q = (float)(Q & ((1u << kQShift<kMod>) - 1u));
     const float r = t * __builtin_amdgcn_sqrtf(St);
     const float e = (float)(rp + 65u) * 0x1p-24f;
     const bool in_range = St >= 0x1p-60f && St <= 0x1p100f;   // false for NaN
@@ -653,10 +706,11 @@ __device__ __forceinline__ PairRuns pair_runs(bool actA, bool contA, bool actB, 
 // A = base + 2l and B = A + 1. Flags, runs, cluster threshold; every lane takes part (no divergent
 // cross-lane work). Adds the flag bits to the digi words, marks accepted run heads and counts
 // clusters / member ADCs.
+template <bool kMod>
 __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t nd, uint32_t dA,
                                           uint32_t dB, float nA, float nB, const DeviceCalib& cal,
-                                          OpenRun& open, uint32_t& n_cl, uint32_t& my_adc,
-                                          uint32_t& pending) {
+                                          const Joins& J, OpenRun& open, uint32_t& n_cl,
+                                          uint32_t& my_adc, uint32_t& pending) {
     const uint32_t l = lane();
     const uint32_t jA = base + 2u * l, jB = jA + 1u;
     const bool vA = jA < nd, vB = jB < nd;
@@ -668,13 +722,19 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
     const bool sdA = actA && afA > cal.t_seed * nA;
     const bool sdB = actB && afB > cal.t_seed * nB;
     // continues the previous digi: both active, same channel, adjacent strips (B follows A in
-    // the lane, A follows the previous lane's B)
+    // the lane, A follows the previous lane's B); in a module row also strip 0 after strip 255 of
+    // the channel before, when the two are joined
     const uint32_t keyA = actA ? pA + 1u : kNoKey;
     const uint32_t keyB = actB ? pB + 1u : kNoKey;
-    const bool contB = actB && d_strip(dB) != 0u && keyA == pB;
+    bool edgeA = d_strip(dA) != 0u, edgeB = d_strip(dB) != 0u;
+    if constexpr (kMod) {
+        edgeA = edgeA || joined(J, d_ch(dA));
+        edgeB = edgeB || joined(J, d_ch(dB));
+    }
+    const bool contB = actB && edgeB && keyA == pB;
     uint32_t pk = from_prev_lane(keyB);
     pk = l == 0u ? open.key : pk;
-    const bool contA = actA && d_strip(dA) != 0u && pk == pA;
+    const bool contA = actA && edgeA && pk == pA;
     const bool cont0 = (__ballot(contA) & 1ull) != 0ull;
     // the run open at the end of the previous step ends before this step
     if (open.key != kNoKey && !cont0 && open.mark) {
@@ -691,8 +751,8 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
     // sums along the runs: noise squares (tree order), raw charge, seeds. Each lane's share of
     // the run of its digi B is summed across lanes; digi A takes the previous lane's total.
     float SA = actA ? nA * nA : 0.0f, SB = actB ? nB * nB : 0.0f;
-    uint32_t QA = actA ? aA + (sdA ? 0x10000u : 0u) : 0u;
-    uint32_t QB = actB ? aB + (sdB ? 0x10000u : 0u) : 0u;
+    uint32_t QA = actA ? aA + (sdA ? 1u << kQShift<kMod> : 0u) : 0u;
+    uint32_t QB = actB ? aB + (sdB ? 1u << kQShift<kMod> : 0u) : 0u;
     if (cont0) {
         const bool l0 = l == 0u;
         SA = l0 ? SA + open.S : SA;
@@ -715,8 +775,8 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
     const bool next_contA = from_next_lane(contA ? 1u : 0u) != 0u;
     const bool endA = actA && !contB;
     const bool endB = actB && !next_contA;
-    const uint32_t markA = cluster_mark(endA, rpA, QA, SA, cal.t_cluster);
-    const uint32_t markB = cluster_mark(endB, rpB, QB, SB, cal.t_cluster);
+    const uint32_t markA = cluster_mark<kMod>(endA, rpA, QA, SA, cal.t_cluster);
+    const uint32_t markB = cluster_mark<kMod>(endB, rpB, QB, SB, cal.t_cluster);
     const bool eB = markB != 0u && l != 63u;
     if (markA) dl[jA - rpA] |= markA;
     if (eB) dl[jB - rpB] |= markB;
@@ -733,8 +793,10 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
 }
 
 // Forming over the digi list dl[0, nd): steps of 128 digis, the loads of kBatch steps in flight.
+template <bool kMod>
 __device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const DeviceCalib& cal,
-                                          uint32_t fed, uint32_t& n_cl, uint32_t& n_adc) {
+                                          uint32_t fed, const Joins& J, uint32_t& n_cl,
+                                          uint32_t& n_adc) {
     constexpr int kBatch = 4;
     constexpr uint32_t kStep = 2 * kWave;
     gconst<float>* noise = gc(cal.noise) + fed * kStripsPerFed;
@@ -761,8 +823,8 @@ __device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const Devic
         for (int k = 0; k < kBatch; ++k) {
             const uint32_t base = b + (uint32_t)k * kStep;
             if (base < nd)
-                form_step(dl, base, nd, dA[k], dB[k], nA[k], nB[k], cal, open, ncl, my_adc,
-                          pending);
+                form_step<kMod>(dl, base, nd, dA[k], dB[k], nA[k], nB[k], cal, J, open, ncl,
+                                my_adc, pending);
         }
     }
     if (open.key != kNoKey && open.mark) {
@@ -789,18 +851,36 @@ struct OpenCluster {
     uint32_t open;   // 1: the last digi of the previous step was a member
     uint32_t acc;    // acceptance of that digi's run (for the digis that continue it)
     uint32_t rp;     // run position of that digi
-    uint32_t C, M;   // sums of c and strip*c so far
+    uint32_t C, M;   // sums of c and strip*c so far (module rows: of the low 16 bits of pos*c)
+    uint32_t Mh;     // module rows: sum of the high bits of pos*c
     u32x4 rec;       // its record as it stands (valid if the cluster ends there)
 };
 
+// Record of the cluster whose last digi is dw, rp positions after its first. Channel runs: M is
+// the sum of strip * c. Module rows: the cluster may start in an earlier channel of the row, so
+// its channel and first strip come from the position of its first digi (d_pos(dw) - rp), and the
+// strip moment from that channel's strip 0 is sum(pos * c) - 256 ch C, with sum(pos * c) =
+// 65536 Mh + M (pos * c < 2^31, summed in two halves so that 768 strips cannot overflow).
+template <bool kMod>
 __device__ __forceinline__ u32x4 make_record(uint32_t fed, uint32_t dw, uint32_t rp, uint32_t C,
-                                             uint32_t M) {
-    const uint32_t strip = d_strip(dw);
-    const uint32_t first = strip - rp, width = rp + 1u;
+                                             uint32_t M, uint32_t Mh) {
+    uint32_t ch, first;
+    double m;
+    if constexpr (kMod) {
+        const uint32_t head = d_pos(dw) - rp;
+        ch = head >> 8;
+        first = head & 255u;
+        m = ((double)Mh * 65536.0 + (double)M) - 256.0 * (double)ch * (double)C;   // exact
+    } else {
+        ch = d_ch(dw);
+        first = d_strip(dw) - rp;
+        m = (double)M;
+    }
+    const uint32_t width = rp + 1u;
     // barycenter: sum (s+1/2) c / sum c = (2M + C) / (2C), numerator and denominator exact
-    const float bary = C ? (float)((2.0 * (double)M + (double)C) / (2.0 * (double)C))
+    const float bary = C ? (float)((2.0 * m + (double)C) / (2.0 * (double)C))
                          : (float)first + (float)width * 0.5f;
-    return u32x4{fed * kNch + d_ch(dw), first | (width << 16), C, __float_as_uint(bary)};
+    return u32x4{fed * kNch + ch, first | (width << 16), C, __float_as_uint(bary)};
 }
 
 // Gain-corrected ADC of a member digi: min(rint(adc / gain), 65535) with the FP32 quotient.
@@ -812,14 +892,14 @@ __device__ __forceinline__ uint32_t corrected_adc(uint32_t d, float g) {
 // Records and member ADCs of the digi list dl[0, nd) at their final positions, 128 digis per
 // step, two per lane (A = base + 2l, B = A + 1) as in forming. The member ADCs are
 // gain-corrected here.
-template <int W, int DW>
+template <bool kMod, int W, int DW>
 __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint32_t* dl,
                                            uint32_t nd, uint32_t fed, const EventDesc& ev,
                                            uint32_t base_cl, uint32_t base_adc) {
     constexpr uint32_t kStep = 2 * kWave;
     gmut<uint16_t>* adc_out = gm(ev.adc);
     gmut<u32x4>* cl_out = gm(reinterpret_cast<u32x4*>(ev.cl));
-    OpenCluster oc{0u, 0u, 0u, 0u, 0u, u32x4{0u, 0u, 0u, 0u}};
+    OpenCluster oc{0u, 0u, 0u, 0u, 0u, 0u, u32x4{0u, 0u, 0u, 0u}};
     uint32_t rc = base_cl, pa = base_adc;
     const uint32_t l = lane();
     // the digi words and APV gains of the next step are read while this step runs
@@ -869,19 +949,40 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         pa += popc(mbA) + popc(mbB);
         // charge and strip-weighted charge along member runs: each lane's share of the run of
         // its digi B is summed across lanes; digi A takes the previous lane's total
-        uint32_t CA = cA, MA = d_strip(dA) * cA;
+        uint32_t CA = cA, MA, MhA = 0u, MB, MhB = 0u;
+        if constexpr (kMod) {
+            const uint32_t mA = d_pos(dA) * cA, mB = d_pos(dB) * cB;
+            MA = mA & 0xffffu;
+            MhA = mA >> 16;
+            MB = mB & 0xffffu;
+            MhB = mB >> 16;
+        } else {
+            MA = d_strip(dA) * cA;
+            MB = d_strip(dB) * cB;
+        }
         if (cont0 && oc.open) {
             const bool l0 = l == 0u;
             CA = l0 ? CA + oc.C : CA;
             MA = l0 ? MA + oc.M : MA;
+            if constexpr (kMod) MhA = l0 ? MhA + oc.Mh : MhA;
         }
-        uint32_t CB = cB + (contB ? CA : 0u), MB = d_strip(dB) * cB + (contB ? MA : 0u);
-        run_sums(CB, MB, pr.lanes);
+        uint32_t CB = cB + (contB ? CA : 0u);
+        MB += contB ? MA : 0u;
+        if constexpr (kMod) {
+            MhB += contB ? MhA : 0u;
+            run_sums3(CB, MB, MhB, pr.lanes);
+        } else {
+            run_sums(CB, MB, pr.lanes);
+        }
         {
             const uint32_t Cp = from_prev_lane(CB), Mp = from_prev_lane(MB);
             const bool in = contA && l != 0u;
             CA = in ? CA + Cp : CA;
             MA = in ? MA + Mp : MA;
+            if constexpr (kMod) {
+                const uint32_t Mhp = from_prev_lane(MhB);
+                MhA = in ? MhA + Mhp : MhA;
+            }
         }
         // records of the clusters ending in this step (A before B in a lane); the record of
         // digi B of lane 63 as it stands is kept for the next step, which stores it if the
@@ -893,12 +994,12 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         // one record per lane first (A's where A ends, else B's), B's too where both end
         u32x4 rec1 = {0u, 0u, 0u, 0u}, recB = {0u, 0u, 0u, 0u};
         if (endA || endB) {
-            rec1 = make_record(fed, endA ? dA : dB, endA ? rpA : rpB, endA ? CA : CB,
-                               endA ? MA : MB);
+            rec1 = make_record<kMod>(fed, endA ? dA : dB, endA ? rpA : rpB, endA ? CA : CB,
+                                     endA ? MA : MB, endA ? MhA : MhB);
         }
         const bool both = endA && endB;
         if (__ballot(both) != 0ull) {
-            if (both) recB = make_record(fed, dB, rpB, CB, MB);
+            if (both) recB = make_record<kMod>(fed, dB, rpB, CB, MB, MhB);
         }
         if (!endA) recB = rec1;
         const uint64_t ebA = __ballot(endA), ebB = __ballot(eB);
@@ -914,6 +1015,7 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         oc.rp = last_lane(rpB);
         oc.C = last_lane(CB);
         oc.M = last_lane(MB);
+        if constexpr (kMod) oc.Mh = last_lane(MhB);
         oc.rec = u32x4{last_lane(recB.x), last_lane(recB.y), last_lane(recB.z), last_lane(recB.w)};
         gnA = gain_of(nA);
         gnB = gain_of(nB);
@@ -991,10 +1093,10 @@ __device__ __forceinline__ void emit_status(TileSmem<W, DW>& sm, uint32_t c_lo, 
 // form their groups, exchange their counts in LDS, and wave 0 publishes the FED's counts and
 // looks back over the earlier FEDs of the event; each group's output offset is then the FED's
 // plus the counts of the groups before it. Every wave passes the same two barriers.
-template <int W, int DW, class BuildFn>
+template <int W, int DW, bool kMod, class BuildFn>
 __device__ void cluster_group(const FusedArgs& A, TileSmem<W, DW>& sm, const EventDesc& ev,
                               uint32_t e, uint32_t f, uint32_t w, uint32_t n_chunks,
-                              BuildFn build) {
+                              const Joins& J, BuildFn build) {
     const uint32_t n_fed = A.cal.n_fed;
     unsigned long long* row = A.tile_state + (size_t)e * n_fed;
     uint32_t* dl = sm.digi + w * DW;
@@ -1005,7 +1107,7 @@ __device__ void cluster_group(const FusedArgs& A, TileSmem<W, DW>& sm, const Eve
         const uint32_t c0 = uni(cf[ci]), c1 = uni(cf[ci + 1]);
         build(c0, c1);
         last_nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
-        form_pass(dl, last_nd, A.cal, f, last_cl, last_adc);
+        form_pass<kMod>(dl, last_nd, A.cal, f, J, last_cl, last_adc);
         n_cl += last_cl;
         n_adc += last_adc;
     }
@@ -1042,15 +1144,15 @@ __device__ void cluster_group(const FusedArgs& A, TileSmem<W, DW>& sm, const Eve
     // writes: the last chunk first (still formed in the list), then the earlier chunks of a
     // chunked group, built and formed again
     const uint32_t bc = ex_cl + pre_cl, ba = ex_adc + pre_adc;
-    write_pass(sm, dl, last_nd, f, ev, bc + n_cl - last_cl, ba + n_adc - last_adc);
+    write_pass<kMod>(sm, dl, last_nd, f, ev, bc + n_cl - last_cl, ba + n_adc - last_adc);
     uint32_t oc = bc, oa = ba;
     for (uint32_t ci = 0; ci + 1 < n_chunks; ++ci) {
         const uint32_t c0 = uni(cf[ci]), c1 = uni(cf[ci + 1]);
         build(c0, c1);
         const uint32_t nd = uni(sm.ch_base[c1 + w] - sm.ch_base[c0 + w]);
         uint32_t ccl, cadc;
-        form_pass(dl, nd, A.cal, f, ccl, cadc);
-        write_pass(sm, dl, nd, f, ev, oc, oa);
+        form_pass<kMod>(dl, nd, A.cal, f, J, ccl, cadc);
+        write_pass<kMod>(sm, dl, nd, f, ev, oc, oa);
         oc += ccl;
         oa += cadc;
     }
@@ -1072,7 +1174,18 @@ __device__ __forceinline__ void group_range(uint32_t w, uint32_t& c_lo, uint32_t
 }
 
 // ---- one (event, FED) tile from ZS bytes --------------------------------------------------
-template <int W, int DW>
+// The FED's join words (module rows), uniform.
+template <bool kMod>
+__device__ __forceinline__ Joins fed_joins(const DeviceCalib& cal, uint32_t f) {
+    if constexpr (kMod) {
+        gconst<uint32_t>* j = gc(cal.joins) + 4u * f;
+        return Joins{uni(j[0]), uni(j[1]), uni(j[2])};
+    } else {
+        return Joins{0u, 0u, 0u};
+    }
+}
+
+template <int W, int DW, bool kMod>
 __device__ void zs_tile(const FusedArgs& A, TileSmem<W, DW>& sm, uint32_t e, uint32_t f) {
     const EventDesc* evp = A.ev + e;
     EventDesc ev;
@@ -1093,14 +1206,17 @@ __device__ void zs_tile(const FusedArgs& A, TileSmem<W, DW>& sm, uint32_t e, uin
     group_range<W>(w, c_lo, c_hi);
     uint32_t total;
     uint32_t n_chunks;
+    const Joins J = fed_joins<kMod>(A.cal, f);
     if (wk.fits) {
         const uint8_t* st = sm.stage + wk.delta;
-        n_chunks = plan_chunks(sm, w, c_lo, c_hi,
-                               [&](uint32_t ch) { return check_channel(sm, st, ch, wk); }, total);
+        n_chunks = plan_chunks<kMod>(sm, w, c_lo, c_hi, J,
+                                     [&](uint32_t ch) { return check_channel(sm, st, ch, wk); },
+                                     total);
     } else {
         gconst<uint8_t>* gg = gc(g);
-        n_chunks = plan_chunks(sm, w, c_lo, c_hi,
-                               [&](uint32_t ch) { return check_channel(sm, gg, ch, wk); }, total);
+        n_chunks = plan_chunks<kMod>(sm, w, c_lo, c_hi, J,
+                                     [&](uint32_t ch) { return check_channel(sm, gg, ch, wk); },
+                                     total);
     }
     emit_status(sm, c_lo, c_hi, ev.chan_status, f, &A.res[e].flags);
     uint32_t* dl = sm.digi + w * DW;
@@ -1110,11 +1226,11 @@ __device__ void zs_tile(const FusedArgs& A, TileSmem<W, DW>& sm, uint32_t e, uin
         if (fits) build_zs<true>(sm, w, dl, (const uint8_t*)(sm.stage + delta), c0, c1);
         else      build_zs<false>(sm, w, dl, gc(g), c0, c1);
     };
-    cluster_group(A, sm, ev, e, f, w, n_chunks, build);
+    cluster_group<W, DW, kMod>(A, sm, ev, e, f, w, n_chunks, J, build);
 }
 
 // ---- one FED tile from dense ADC rows (single event) --------------------------------------
-template <int W, int DW>
+template <int W, int DW, bool kMod>
 __device__ void dense_tile(const FusedArgs& A, TileSmem<W, DW>& sm, const uint8_t* dense,
                            uint32_t f) {
     const EventDesc* evp = A.ev;
@@ -1134,12 +1250,13 @@ __device__ void dense_tile(const FusedArgs& A, TileSmem<W, DW>& sm, const uint8_
     group_range<W>(w, c_lo, c_hi);
     for (uint32_t ch = c_lo + lane(); ch < c_hi; ch += kWave) sm.ch_st[ch] = 0;
     uint32_t total;
-    const uint32_t n_chunks = plan_chunks(
-        sm, w, c_lo, c_hi,
+    const Joins J = fed_joins<kMod>(A.cal, f);
+    const uint32_t n_chunks = plan_chunks<kMod>(
+        sm, w, c_lo, c_hi, J,
         [&](uint32_t ch) { return count_dense_row(rows + ch * kStripsPerChannel); }, total);
     uint32_t* dl = sm.digi + w * DW;
     auto build = [&](uint32_t c0, uint32_t c1) { build_dense(sm, w, dl, rows, c0, c1); };
-    cluster_group(A, sm, ev, 0, f, w, n_chunks, build);
+    cluster_group<W, DW, kMod>(A, sm, ev, 0, f, w, n_chunks, J, build);
 }
 
 // ---- kernels --------------------------------------------------------------------------------
@@ -1256,20 +1373,20 @@ __device__ __forceinline__ void run_tiles(TileSmem<W, DW>& sm, uint32_t* queue, 
     }
 }
 
-template <int W, int DW>
+template <int W, int DW, bool kMod>
 __global__ __launch_bounds__(kWave * W) void fused_kernel(FusedArgs A) {
     __shared__ TileSmem<W, DW> sm;
     // the ZS build finds its record markers by bit 31 of the digi list's slots: clear them once
     for (uint32_t i = threadIdx.x; i < (uint32_t)(W * DW); i += kWave * W) sm.digi[i] = 0u;
     run_tiles(sm, A.queue, A.n_ev, A.cal.n_fed, A.fed_major,
-              [&](uint32_t e, uint32_t f) { zs_tile<W, DW>(A, sm, e, f); });
+              [&](uint32_t e, uint32_t f) { zs_tile<W, DW, kMod>(A, sm, e, f); });
 }
 
-template <int W, int DW>
+template <int W, int DW, bool kMod>
 __global__ __launch_bounds__(kWave * W) void cluster_dense_kernel(const uint8_t* dense, FusedArgs A) {
     __shared__ TileSmem<W, DW> sm;
     run_tiles(sm, A.queue, 1u, A.cal.n_fed, 1u,
-              [&](uint32_t, uint32_t f) { dense_tile<W, DW>(A, sm, dense, f); });
+              [&](uint32_t, uint32_t f) { dense_tile<W, DW, kMod>(A, sm, dense, f); });
 }
 
 // ZS -> dense rows, one FED per single-wave workgroup.
@@ -1285,12 +1402,12 @@ __global__ __launch_bounds__(kWave) void unpack_kernel(const uint8_t* zs, const 
     uint32_t total;
     if (w.fits) {
         const uint8_t* st = sm.stage + w.delta;
-        plan_chunks(sm, 0u, 0u, (uint32_t)kNch,
-                    [&](uint32_t ch) { return check_channel(sm, st, ch, w); }, total);
+        plan_chunks<false>(sm, 0u, 0u, (uint32_t)kNch, Joins{0u, 0u, 0u},
+                           [&](uint32_t ch) { return check_channel(sm, st, ch, w); }, total);
     } else {
         gconst<uint8_t>* gg = gc(g);
-        plan_chunks(sm, 0u, 0u, (uint32_t)kNch,
-                    [&](uint32_t ch) { return check_channel(sm, gg, ch, w); }, total);
+        plan_chunks<false>(sm, 0u, 0u, (uint32_t)kNch, Joins{0u, 0u, 0u},
+                           [&](uint32_t ch) { return check_channel(sm, gg, ch, w); }, total);
     }
     emit_status(sm, 0u, (uint32_t)kNch, chan_status, f, &res->flags);
     // 16 channels at a time: zero rows in LDS, expand records, copy out with 16-byte stores
@@ -1356,17 +1473,20 @@ __global__ void derive_calib_kernel(const float* noise, const float* gain, const
 }
 
 // Resident tiles per CU of a kernel (its LDS and registers), queried once per shape.
-template <int W, int DW>
+template <int W, int DW, bool kMod>
 int blocks_per_cu_for(bool dense) {
     static std::atomic<int> known[2] = {0, 0};
     int nb = known[dense].load(std::memory_order_relaxed);
     if (nb > 0) return nb;
-    hipError_t e = dense ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cluster_dense_kernel<W, DW>, kWave * W, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_kernel<W, DW>, kWave * W, 0);
+    hipError_t e = dense ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cluster_dense_kernel<W, DW, kMod>, kWave * W, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_kernel<W, DW, kMod>, kWave * W, 0);
     if (e != hipSuccess || nb < 1) return 1;
     known[dense].store(nb, std::memory_order_relaxed);
     return nb;
 }
+
+// Module rows need a whole row (up to 768 digis) in one chunk of a wave's list.
+constexpr int kRowDigis = 3 * kStripsPerChannel;
 
 // Tile shapes: W waves per tile and chunk_digis digis per tile (chunk_digis / W per wave).
 template <class F>
@@ -1386,10 +1506,21 @@ bool tile_shape_supported(uint32_t waves, uint32_t d) {
     return dispatch(waves, d, [](auto, auto) {});
 }
 
-int fused_blocks_per_cu(uint32_t waves, uint32_t d, bool dense) {
+bool tile_shape_supports_modules(uint32_t waves, uint32_t d) {
+    bool ok = false;
+    dispatch(waves, d, [&](auto, auto DW) { ok = decltype(DW)::value >= kRowDigis; });
+    return ok;
+}
+
+int fused_blocks_per_cu(uint32_t waves, uint32_t d, bool dense, bool modules) {
     int nb = 1;
     dispatch(waves, d, [&](auto W, auto DW) {
-        nb = blocks_per_cu_for<decltype(W)::value, decltype(DW)::value>(dense);
+        constexpr int w = decltype(W)::value, dw = decltype(DW)::value;
+        if constexpr (dw >= kRowDigis) {
+            nb = modules ? blocks_per_cu_for<w, dw, true>(dense) : blocks_per_cu_for<w, dw, false>(dense);
+        } else {
+            nb = blocks_per_cu_for<w, dw, false>(dense);
+        }
     });
     return nb;
 }
@@ -1414,12 +1545,22 @@ hipError_t launch_reset(const FusedArgs& a, uint32_t n_state, hipStream_t stream
     return hipGetLastError();
 }
 
+// The module-row kernels (cal.joins set) exist for the shapes whose wave lists hold a row.
 hipError_t launch_fused(const FusedArgs& a, uint32_t waves, uint32_t d, uint32_t grid,
                         hipStream_t stream) {
     (void)hipGetLastError();
-    const bool ok = dispatch(waves, d, [&](auto W, auto DW) {
+    const bool mod = a.cal.joins != nullptr;
+    bool ok = false;
+    dispatch(waves, d, [&](auto W, auto DW) {
         constexpr int w = decltype(W)::value, dw = decltype(DW)::value;
-        hipLaunchKernelGGL((fused_kernel<w, dw>), dim3(grid), dim3(kWave * w), 0, stream, a);
+        if constexpr (dw >= kRowDigis) {
+            if (mod) hipLaunchKernelGGL((fused_kernel<w, dw, true>), dim3(grid), dim3(kWave * w), 0, stream, a);
+            else     hipLaunchKernelGGL((fused_kernel<w, dw, false>), dim3(grid), dim3(kWave * w), 0, stream, a);
+            ok = true;
+        } else if (!mod) {
+            hipLaunchKernelGGL((fused_kernel<w, dw, false>), dim3(grid), dim3(kWave * w), 0, stream, a);
+            ok = true;
+        }
     });
     return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
@@ -1427,10 +1568,18 @@ hipError_t launch_fused(const FusedArgs& a, uint32_t waves, uint32_t d, uint32_t
 hipError_t launch_cluster_dense(const uint8_t* dense, const FusedArgs& a, uint32_t waves,
                                 uint32_t d, uint32_t grid, hipStream_t stream) {
     (void)hipGetLastError();
-    const bool ok = dispatch(waves, d, [&](auto W, auto DW) {
+    const bool mod = a.cal.joins != nullptr;
+    bool ok = false;
+    dispatch(waves, d, [&](auto W, auto DW) {
         constexpr int w = decltype(W)::value, dw = decltype(DW)::value;
-        hipLaunchKernelGGL((cluster_dense_kernel<w, dw>), dim3(grid), dim3(kWave * w), 0, stream,
-                           dense, a);
+        if constexpr (dw >= kRowDigis) {
+            if (mod) hipLaunchKernelGGL((cluster_dense_kernel<w, dw, true>), dim3(grid), dim3(kWave * w), 0, stream, dense, a);
+            else     hipLaunchKernelGGL((cluster_dense_kernel<w, dw, false>), dim3(grid), dim3(kWave * w), 0, stream, dense, a);
+            ok = true;
+        } else if (!mod) {
+            hipLaunchKernelGGL((cluster_dense_kernel<w, dw, false>), dim3(grid), dim3(kWave * w), 0, stream, dense, a);
+            ok = true;
+        }
     });
     return ok ? hipGetLastError() : hipErrorInvalidValue;
 }

@@ -130,11 +130,11 @@ struct Workspace {
 size_t devbuf_size(size_t bytes) { return bytes ? align_up(std::max<size_t>(bytes, 256), 4096) : 0; }
 
 struct GraphKey {
-    uint32_t n_ev, chunk, waves, grid, fed_major;
+    uint32_t n_ev, chunk, waves, grid, fed_major, modules;
     uint64_t gen;
     bool operator<(const GraphKey& o) const {
-        return std::tie(n_ev, chunk, waves, grid, fed_major, gen) <
-               std::tie(o.n_ev, o.chunk, o.waves, o.grid, o.fed_major, o.gen);
+        return std::tie(n_ev, chunk, waves, grid, fed_major, modules, gen) <
+               std::tie(o.n_ev, o.chunk, o.waves, o.grid, o.fed_major, o.modules, o.gen);
     }
 };
 
@@ -178,6 +178,10 @@ struct sc_ctx {
     DevBuf geo_chan, geo_mod, hit_desc;
     PinBuf h_hit_desc;
     uint32_t geo_modules = 0;
+    // module rows (sc_set_modules): per FED four words, bit c set when channel c continues the
+    // module of channel c - 1
+    DevBuf d_joins;
+    bool modules = false;
     hipStream_t pipe_h2d = nullptr, pipe_d2h = nullptr;
     hipEvent_t pipe_in[2] = {nullptr, nullptr}, pipe_done[2] = {nullptr, nullptr};
 };
@@ -224,7 +228,8 @@ sc_status device_fail(sc_ctx* c, hipError_t e, const char* where) {
     } while (0)
 
 uint32_t grid_for(const sc_ctx* c, uint32_t n_tiles, bool dense) {
-    const int occ = std::max(1, fused_blocks_per_cu(c->tuning.tile_waves, c->tuning.chunk_digis, dense));
+    const int occ = std::max(1, fused_blocks_per_cu(c->tuning.tile_waves, c->tuning.chunk_digis,
+                                                    dense, c->modules));
     const uint32_t per_cu = std::max<uint32_t>(1, std::min<uint32_t>(c->tuning.tiles_per_cu, occ));
     const uint32_t g = per_cu * (uint32_t)std::max(1, c->n_cu);
     return std::max<uint32_t>(1, std::min<uint32_t>(g, n_tiles));
@@ -433,6 +438,7 @@ FusedArgs fused_args(sc_ctx* c, Workspace& ws, uint32_t n) {
     a.queue = ws.queue.as<uint32_t>();
     a.cal.noise = c->d_noise;
     a.cal.gain = c->d_gain;
+    a.cal.joins = c->modules ? c->d_joins.as<uint32_t>() : nullptr;
     a.cal.n_fed = c->n_fed;
     a.cal.t_seed = c->t_seed;
     a.cal.t_channel = c->t_channel;
@@ -486,7 +492,7 @@ hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bo
 hipError_t enqueue_batch_graph(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s) {
     const uint32_t grid = grid_for(c, n * c->n_fed, false);
     GraphKey k{n, c->tuning.chunk_digis, c->tuning.tile_waves, grid, c->tuning.fed_major,
-               ws.generation};
+               c->modules ? 1u : 0u, ws.generation};
     auto it = c->graphs.find(k);
     hipError_t e;
     if (it == c->graphs.end()) {
@@ -1048,6 +1054,7 @@ void sc_destroy(sc_ctx* c) {
     c->ws.release();
     c->h_static.release();
     c->geo_chan.release();
+    c->d_joins.release();
     c->geo_mod.release();
     c->hit_desc.release();
     c->h_hit_desc.release();
@@ -1185,6 +1192,46 @@ sc_status sc_process_events(sc_ctx* c, const sc_event* ev, uint32_t n, sc_cluste
     }
     SC_HIP(c, hipSetDevice(c->device));
     return run_batch(c, ev, n, out, ev_status, all_device);
+}
+
+sc_status sc_set_modules(sc_ctx* c, const uint32_t* channel_module) {
+    if (!c) return SC_ERR_INVALID_ARG;
+    if (c->poisoned) return SC_ERR_DEVICE;
+    if (!channel_module) {
+        c->modules = false;
+        return SC_OK;
+    }
+    if (!tile_shape_supports_modules(c->tuning.tile_waves, c->tuning.chunk_digis))
+        return fail(c, SC_ERR_INVALID_ARG,
+                    "sc_set_modules: the current tile shape holds no module row (768 digis per "
+                    "wave); choose another chunk_digis or tile_waves first");
+    std::vector<uint32_t> words(4 * (size_t)c->n_fed, 0u);
+    for (uint32_t f = 0; f < c->n_fed; ++f) {
+        const uint32_t* m = channel_module + (size_t)f * kChannelsPerFed;
+        uint32_t row = 1;
+        for (uint32_t ch = 1; ch < (uint32_t)kChannelsPerFed; ++ch) {
+            if (m[ch] != m[ch - 1]) {
+                row = 1;
+                continue;
+            }
+            if (ch % 24u == 0u)
+                return fail(c, SC_ERR_INVALID_ARG,
+                            "sc_set_modules: a module crosses a multiple of 24 channels of a FED");
+            if (++row > 3u)
+                return fail(c, SC_ERR_INVALID_ARG,
+                            "sc_set_modules: a module spans more than 3 consecutive channels");
+            words[4 * (size_t)f + ch / 32u] |= 1u << (ch % 32u);
+        }
+    }
+    SC_HIP(c, hipSetDevice(c->device));
+    // wait for work that may read the old words before they are overwritten
+    SC_HIP(c, hipStreamSynchronize(c->stream));
+    SC_HIP(c, c->d_joins.ensure(sizeof(uint32_t) * words.size()));
+    SC_HIP(c, hipMemcpyAsync(c->d_joins.p, words.data(), sizeof(uint32_t) * words.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    SC_HIP(c, hipStreamSynchronize(c->stream));
+    c->modules = true;
+    return SC_OK;
 }
 
 sc_status sc_set_geometry(sc_ctx* c, const sc_geometry* g) {
@@ -1397,6 +1444,7 @@ sc_status sc_process_events_static(sc_ctx* c, const sc_event* ev, uint32_t n, sc
     a.queue = reinterpret_cast<uint32_t*>(c->d_static + kStaticQueueOff);
     a.cal.noise = c->d_noise;
     a.cal.gain = c->d_gain;
+    a.cal.joins = c->modules ? c->d_joins.as<uint32_t>() : nullptr;
     a.cal.n_fed = c->n_fed;
     a.cal.t_seed = c->t_seed;
     a.cal.t_channel = c->t_channel;
@@ -1553,6 +1601,9 @@ sc_status sc_set_tuning(sc_ctx* c, const sc_tuning* t) {
         return fail(c, SC_ERR_INVALID_ARG,
                     "unsupported tuning (tile_waves 1, 2 or 4; chunk_digis 2048, 3072 or 4096, "
                     "1024 with one wave, 2880 with two)");
+    if (c->modules && !tile_shape_supports_modules(t->tile_waves, t->chunk_digis))
+        return fail(c, SC_ERR_INVALID_ARG,
+                    "tile shape holds no module row (768 digis per wave) while modules are set");
     c->tuning = *t;
     c->tuning.fed_major = t->fed_major > 2u ? 1u : t->fed_major;
     c->tuning.use_graph = t->use_graph ? 1 : 0;
@@ -1604,14 +1655,16 @@ sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best
     for (uint32_t w : {1u, 2u, 4u})
         for (uint32_t d : {1024u, 2048u, 2880u, 3072u, 4096u})
             for (uint32_t fm : {0u, 1u, 2u})
-                if (tile_shape_supported(w, d)) cands.push_back(sc_tuning{d, w, 32, fm, 0});
+                if (tile_shape_supported(w, d) && (!c->modules || tile_shape_supports_modules(w, d)))
+                    cands.push_back(sc_tuning{d, w, 32, fm, 0});
     const size_t n_stage1 = cands.size();
     std::vector<uint8_t> ref_cl, ref_adc, cur_cl, cur_adc;
     double best_ms = 1e30;
     sc_tuning best_t = saved;
     for (size_t ci = 0; ci < cands.size(); ++ci) {
         if (ci == n_stage1) {
-            const int occ = fused_blocks_per_cu(best_t.tile_waves, best_t.chunk_digis, false);
+            const int occ = fused_blocks_per_cu(best_t.tile_waves, best_t.chunk_digis, false,
+                                                c->modules);
             for (int tpc = occ - 1; tpc >= std::max(1, occ - 3); --tpc) {
                 sc_tuning t = best_t;
                 t.tiles_per_cu = (uint32_t)tpc;
