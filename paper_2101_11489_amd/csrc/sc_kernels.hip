@@ -207,7 +207,7 @@ __device__ __forceinline__ uint32_t d_pos(uint32_t d) { return (d >> 8) & 0x7fff
 struct Joins {
     uint32_t w0, w1, w2;
 };
-__device__ __forceinline__ bool joined(const Joins& J, uint32_t ch) {
+__device__ __forceinline__ bool joined(Joins J, uint32_t ch) {
     const uint32_t w = ch < 32u ? J.w0 : ch < 64u ? J.w1 : J.w2;
     return ((w >> (ch & 31u)) & 1u) != 0u;
 }
@@ -433,7 +433,7 @@ __device__ __forceinline__ uint32_t check_channel(TileSmem<W, DW>& sm, P src, ui
 // its split into chunks of at most DW digis; returns the number of chunks. Wave-local.
 template <bool kMod, int W, int DW, class CountFn>
 __device__ uint32_t plan_chunks(TileSmem<W, DW>& sm, uint32_t w, uint32_t c_lo, uint32_t c_hi,
-                                const Joins& J, CountFn count, uint32_t& total) {
+                                Joins J, CountFn count, uint32_t& total) {
     uint32_t carry = 0;
     for (uint32_t base = c_lo; base < c_hi; base += kWave) {
         const uint32_t ch = base + lane();
@@ -709,7 +709,7 @@ __device__ __forceinline__ PairRuns pair_runs(bool actA, bool contA, bool actB, 
 template <bool kMod>
 __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t nd, uint32_t dA,
                                           uint32_t dB, float nA, float nB, const DeviceCalib& cal,
-                                          const Joins& J, OpenRun& open, uint32_t& n_cl,
+                                          Joins J, OpenRun& open, uint32_t& n_cl,
                                           uint32_t& my_adc, uint32_t& pending) {
     const uint32_t l = lane();
     const uint32_t jA = base + 2u * l, jB = jA + 1u;
@@ -795,7 +795,7 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
 // Forming over the digi list dl[0, nd): steps of 128 digis, the loads of kBatch steps in flight.
 template <bool kMod>
 __device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const DeviceCalib& cal,
-                                          uint32_t fed, const Joins& J, uint32_t& n_cl,
+                                          uint32_t fed, Joins J, uint32_t& n_cl,
                                           uint32_t& n_adc) {
     constexpr int kBatch = 4;
     constexpr uint32_t kStep = 2 * kWave;
@@ -1096,7 +1096,7 @@ __device__ __forceinline__ void emit_status(TileSmem<W, DW>& sm, uint32_t c_lo, 
 template <int W, int DW, bool kMod, class BuildFn>
 __device__ void cluster_group(const FusedArgs& A, TileSmem<W, DW>& sm, const EventDesc& ev,
                               uint32_t e, uint32_t f, uint32_t w, uint32_t n_chunks,
-                              const Joins& J, BuildFn build) {
+                              Joins J, BuildFn build) {
     const uint32_t n_fed = A.cal.n_fed;
     unsigned long long* row = A.tile_state + (size_t)e * n_fed;
     uint32_t* dl = sm.digi + w * DW;

@@ -85,13 +85,19 @@ def test_graph_replay_and_rows_off_again(full):
         ctx.tuning = {"use_graph": 0}
 
 
-def test_dense_path_with_module_rows(full):
+@pytest.mark.parametrize("waves,chunk", MOD_SHAPES)
+def test_dense_path_with_module_rows(full, waves, chunk):
     cal, geo, evs, refs, ctx = full
-    ev = sc.Event(evs[1].zs, evs[1].fed_offset).to_device()
-    dense, _ = ctx.unpack(ev)
-    out = ctx.output(*sc.safe_caps(sc.Event(evs[1].zs, evs[1].fed_offset)))
-    ctx.cluster(dense, out)
-    compare_clusters(*out.to_numpy()[:2], refs[1], "dense path, module rows")
+    before = ctx.tuning
+    ctx.tuning = {"use_graph": 0, "tile_waves": waves, "chunk_digis": chunk}
+    try:
+        ev = sc.Event(evs[1].zs, evs[1].fed_offset).to_device()
+        dense, _ = ctx.unpack(ev)
+        out = ctx.output(*sc.safe_caps(sc.Event(evs[1].zs, evs[1].fed_offset)))
+        ctx.cluster(dense, out)
+        compare_clusters(*out.to_numpy()[:2], refs[1], f"dense path, module rows {waves}x{chunk}")
+    finally:
+        ctx.tuning = before
 
 
 def test_stress_distribution_with_module_rows():
