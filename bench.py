@@ -125,17 +125,31 @@ def cpu_baseline(events, cal, n_fed, seconds, procs, geo):
     GPU results are checked against."""
     import oracle
     from oracle.hits import cluster_hits
+    from oracle.nested import NestedRunner
     refs = {}
     for i in (0, len(events) - 1):
         r = oracle.process_event(events[i].zs, events[i].fed_offset, cal.noise, cal.gain, cal.bad)
         refs[i] = (r.cl, r.adc, cluster_hits(r.cl, geo))
+    cm = geo.channel_module.astype(np.int64)
+    joins = np.zeros(cm.size, np.uint8)
+    joins[1:] = (cm[1:] == cm[:-1]) & (np.arange(1, cm.size) % 96 != 0)
+    rm = oracle.process_event(events[0].zs, events[0].fed_offset, cal.noise, cal.gain, cal.bad,
+                              joins=joins)
+    mod_ref = (rm.cl, rm.adc)
     _CPU_JOB.update(events=events, cal=cal, n_fed=n_fed)
     done1, s1 = _oracle_worker((0, 1, seconds))
     ctx = mp.get_context("fork")
     with ctx.Pool(procs) as pool:
         res = pool.map(_oracle_worker, [(i, procs, seconds) for i in range(procs)])
     agg = sum(d for d, _ in res) / max(s for _, s in res)
-    return refs, {
+    # nested parallelism (paper §3): N events in flight x M FED ranges each, N x M = procs threads
+    nested = []
+    for n_out, n_in in ((procs, 1), (max(1, procs // 4), 4), (1, procs)):
+        d, secs, lat = NestedRunner(events, cal, n_out, n_in).run(seconds / 2)
+        nested.append({"events_in_flight": n_out, "fed_ranges_per_event": n_in,
+                       "threads": n_out * n_in, "events_per_s": d / secs,
+                       "latency_ms_p50": 1e3 * float(np.median(lat)) if lat else None})
+    return refs, mod_ref, {
         "value": agg, "unit": "events/s", "cores": procs, "kind": "oracle",
         "sample": f"the batch's {len(events)} events cycled for {seconds:.0f} s by each of {procs} "
                   f"single-threaded oracle processes (one per core of the box's share; "
@@ -143,6 +157,9 @@ def cpu_baseline(events, cal, n_fed, seconds, procs, geo):
         "single_core_value": done1 / s1,
         "single_core_sample": f"{done1} events in {s1:.1f} s, one process",
         "cpu_model": host_cpu(), "host_cpus_visible": os.cpu_count(),
+        "nested": nested,
+        "nested_sample": f"the batch's events cycled for {seconds / 2:.0f} s per split, each "
+                         "event's 440 FEDs cut into M ranges run at once, N events in flight",
     }
 
 
@@ -453,6 +470,7 @@ def main():
     ap.add_argument("--no-cold", action="store_true")
     ap.add_argument("--no-ingest", action="store_true")
     ap.add_argument("--no-hits", action="store_true")
+    ap.add_argument("--no-modules", action="store_true")
     ap.add_argument("--serve-events", type=int, default=2000,
                     help="events per arrival-rate point of the serving sweep")
     ap.add_argument("--tuning", default=None,
@@ -490,10 +508,11 @@ def main():
         f"ZS {sum(e.zs.size for e in events) / 1e6:.1f} MB")
 
     # ---- CPU baseline first, before anything touches the GPU (its processes are forked) -----
-    cpu, refs = None, None
+    cpu, refs, mod_ref = None, None, None
     geo = fedgen.make_geometry(cfg)
     if not args.no_cpu_baseline and not args.copy_probe_mib:
-        refs, cpu = cpu_baseline(events, cal, n_fed, args.cpu_seconds, args.cpu_procs, geo)
+        refs, mod_ref, cpu = cpu_baseline(events, cal, n_fed, args.cpu_seconds, args.cpu_procs,
+                                          geo)
         log(f"cpu baseline: {cpu}")
 
     import torch
@@ -620,6 +639,38 @@ def main():
         log(f"hits: {hits_line}")
         del hit_bufs
 
+    # ---- module rows: the same batch with runs continuing across the channels of a module ---
+    mod_line = None
+    if not args.no_modules:
+        ctx.tuning = {"use_graph": 0}
+        ctx.set_modules(geo.channel_module)
+        ks = []
+        for _ in range(3 + 20):
+            ctx.process_batch(batch)
+            ks.append(ctx.stats()["last_kernel_ms"])
+        torch.cuda.synchronize()
+        mod_ok = None
+        if mod_ref is not None:
+            rcl, radc = mod_ref
+            cl, adc, _ = outs[0].to_numpy()
+            mod_ok = bool(np.array_equal(cl, rcl) and np.array_equal(adc, radc))
+        n_cross = int(np.sum(outs[0].to_numpy()[0]["first"].astype(np.int64) +
+                             outs[0].to_numpy()[0]["width"] > 256))
+        ctx.set_modules(None)
+        ctx.tuning = {"use_graph": 1}
+        k_mod = statistics.mean(ks[3:])
+        mod_line = {
+            "workload": f"the {n_ev}-event batch with the synthetic module map "
+                        f"({geo.n_modules} modules of 2-3 channels), eager launches",
+            "kernel_ms": k_mod, "events_per_s_kernel": n_ev / (k_mod * 1e-3),
+            "clusters_crossing_a_channel_edge_event0": n_cross,
+            "parity": ("bit-exact against the module-aware oracle (first event)" if mod_ok
+                       else "skipped" if mod_ok is None else "MISMATCH"),
+        }
+        log(f"modules: {mod_line}")
+        # the plain results again for whatever follows
+        ctx.process_batch(batch)
+
     ingest = None
     if not args.no_ingest:
         ctx.tuning = {"use_graph": 0}
@@ -680,6 +731,7 @@ def main():
         "eager": eager,
         "cache_cold": cold,
         "plain_path": plain or None,
+        "module_rows": mod_line,
         "cluster_hits": hits_line,
         "host_ingest": ingest,
         "stress": stress,
