@@ -97,6 +97,32 @@ def test_pipelined_host_ingest_exact(full, batch, layout):
         np.testing.assert_array_equal(a[1], b[1])
 
 
+def test_pipelined_small_calls_and_host_outputs(full):
+    """Batch larger than n; an odd n; host outputs with channel status; page-locked events
+    through the server (copied at submit like pageable ones)."""
+    cal, evs, refs, ctx = full
+    hosts = [sc.Event(e.zs, e.fed_offset) for e in evs]
+    pinned = sc.pack_pinned(hosts)
+    o1 = [ctx.output(*sc.safe_caps(hosts[2]))]
+    rc, sts = ctx.process_pipelined([pinned[2]], o1, 8)
+    assert rc == sc.SC_OK and sts == [sc.SC_OK]
+    compare_clusters(*o1[0].to_numpy()[:2], refs[2], "one event, batch 8")
+    outs = [ctx.output(*sc.safe_caps(h), device=False, chan_status=True) for h in hosts[:5]]
+    rc, sts = ctx.process_pipelined(pinned[:5], outs, 2)
+    assert rc == sc.SC_OK
+    for i, o in enumerate(outs):
+        cl, adc, st = o.to_numpy()
+        compare_clusters(cl, adc, refs[i], f"host outputs {i}")
+        np.testing.assert_array_equal(st, refs[i].chan_status)
+    with make_ctx(cal.noise, cal.gain, cal.bad, max_batch=2, n_streams=2) as srv:
+        souts = [srv.output(*sc.safe_caps(h)) for h in hosts[:4]]
+        tickets = [srv.submit(p, o) for p, o in zip(pinned[:4], souts)]
+        for t in tickets:
+            assert srv.poll(t, -1) == sc.SC_OK
+        for i, o in enumerate(souts):
+            compare_clusters(*o.to_numpy()[:2], refs[i], f"served page-locked {i}")
+
+
 def test_pipelined_statuses_per_event(full):
     """An event whose outputs are too small overflows alone; the others of its batch and of the
     other batches are exact, and a second call on the same context reuses the slots."""

@@ -125,3 +125,23 @@ def test_geometry_and_argument_errors(setup):
         _check(h.cpu().numpy(), outs[0].to_numpy()[0], geo, "fresh context")
     finally:
         fresh.close()
+
+
+def test_more_events_than_one_launch_covers(setup):
+    """65,537 outputs (one launch covers at most 65,535 events): the first and the last carry
+    full events, the rest are empty; the hits of both full ones match the oracle."""
+    cfg, cal, geo, evs, ctx, outs = setup
+    ctx.set_geometry(geo)
+    empty = ctx.output(16, 16)
+    empty.cs.n_cl = 0
+    many = [outs[0]] + [empty] * 65535 + [outs[1]]
+    rows = [max(1, min(o.cs.n_cl, o.cs.cap_cl)) for o in (outs[0], empty, outs[1])]
+    big = torch.empty((rows[0] + 65535 * rows[1] + rows[2], 4), dtype=torch.float32, device="cuda")
+    views, at = [], 0
+    for k in range(len(many)):
+        r = rows[0] if k == 0 else rows[2] if k == len(many) - 1 else rows[1]
+        views.append(big[at:at + r])
+        at += r
+    got = ctx.cluster_hits(many, hits=views)
+    _check(got[0].cpu().numpy(), outs[0].to_numpy()[0], geo, "first of 65537")
+    _check(got[-1].cpu().numpy(), outs[1].to_numpy()[0], geo, "last of 65537")
