@@ -479,6 +479,8 @@ def main():
     ap.add_argument("--serve-only", type=float, default=None, metavar="FRAC",
                     help="only run the serving replay at this fraction of the batched capacity "
                          "(default tuning) and print its JSON")
+    ap.add_argument("--ingest-only", action="store_true",
+                    help="only run the host-ingest measurement on the batch and print its JSON")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB 5 times (reference "
                          "for the HBM byte counters) and exit")
@@ -533,6 +535,11 @@ def main():
     ctx = sc.Context(cal.noise, cal.gain, cal.bad, device=0, stream=stream)
     devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in events]
     outs = [ctx.output(*sc.safe_caps(d)) for d in devs]
+    if args.ingest_only:
+        ctx.tuning = {"use_graph": 0}
+        print(json.dumps(ingest_line(sc, torch, ctx, events, outs, len(events), 8)))
+        ctx.close()
+        return
     torch.cuda.synchronize()
     if args.tuning:
         c, w, t, f = (int(x) for x in args.tuning.split(",")[:4])
