@@ -155,8 +155,12 @@ typedef struct {
                                 reused from cache by its events); 2 FED-major with the FEDs dealt
                                 to one queue per XCD (reused from one L2 instead of eight). The
                                 synchronous calls run order-2 launches one at a time per process;
-                                the server's launches use order 1 in its place. Other values
-                                are taken as 1. */
+                                the server's launches use order 1 in its place. Processes that
+                                share a GPU and launch at the same time should use 0 or 1: an
+                                order-2 launch needs its whole grid resident, and two of them
+                                from different processes can hold each other's compute units
+                                until the look-back's wait bound reports SC_ERR_DEVICE. Other
+                                values are taken as 1. */
     uint32_t use_graph;      /* 1: replay the batched launch as a captured hipGraph */
 } sc_tuning;
 
