@@ -477,7 +477,8 @@ hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bo
     // the per-XCD order needs its whole grid resident with no other such launch running: only a
     // launch that holds order2_mu to its end (the synchronous calls) uses it
     if (!exclusive && a.fed_major == 2u) a.fed_major = 1u;
-    if (capturing || !ws.clean) {
+    // a captured graph holds no reset: its replays reset first, outside the graph, when needed
+    if (!capturing && !ws.clean) {
         if ((e = launch_reset(a, n * c->n_fed, s))) return e;
     }
     if (timed && (e = hipEventRecord(c->ev0, s))) return e;
@@ -513,6 +514,8 @@ hipError_t enqueue_batch_graph(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t
         c->stats.graph_captures++;
     }
     c->stats.graph_replays++;
+    // look-back words, queues and results cleared unless the last call's clean-up already did
+    if (!ws.clean && (e = launch_reset(fused_args(c, ws, n), n * c->n_fed, s))) return e;
     const EventDesc* hd = ws.h_desc.as<EventDesc>();
     ws.desc_on_device.assign(hd, hd + n);   // the replay uploads the current descriptors
     ws.clean = false;
