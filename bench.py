@@ -82,15 +82,23 @@ def load_traffic(workload, tuning):
 
 
 def host_cpu():
-    model = "unknown"
+    """The host CPU as /proc/cpuinfo names it: model name, family / model / stepping, clock."""
+    fields = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
+            if ":" not in line:
+                if fields:
+                    break
+                continue
+            k, v = (x.strip() for x in line.split(":", 1))
+            if k in ("model name", "cpu family", "model", "stepping", "cpu MHz") and k not in fields:
+                fields[k] = v
     except OSError:
         pass
-    return model
+    name = fields.get("model name", "unknown")
+    extra = ", ".join(f"{k} {fields[k]}" for k in ("cpu family", "model", "stepping", "cpu MHz")
+                      if k in fields)
+    return f"{name} ({extra})" if extra else name
 
 
 # ---- the oracle on host cores -----------------------------------------------------------------
