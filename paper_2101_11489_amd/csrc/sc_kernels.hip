@@ -96,50 +96,21 @@ template <int Ctrl, int RowMask>
 __device__ __forceinline__ uint32_t dpp_in(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, RowMask, 0xf, true);
 }
-__device__ __forceinline__ uint32_t as_bits(float x) { return __float_as_uint(x); }
-__device__ __forceinline__ uint32_t as_bits(uint32_t x) { return x; }
-__device__ __forceinline__ void add_if(float& x, uint32_t y, bool c) {
-    x = c ? x + __uint_as_float(y) : x;
-}
-__device__ __forceinline__ void add_if(uint32_t& x, uint32_t y, bool c) { x = c ? x + y : x; }
-
-template <int Ctrl, int RowMask, class A, class B>
-__device__ __forceinline__ void run_sum_step(A& a, B& b, bool c) {
-    const uint32_t ya = dpp_in<Ctrl, RowMask>(as_bits(a));
-    const uint32_t yb = dpp_in<Ctrl, RowMask>(as_bits(b));
-    add_if(a, ya, c);
-    add_if(b, yb, c);
-}
-
-template <class A, class B>
-__device__ __forceinline__ void run_sums(A& a, B& b, uint32_t r) {
-    const uint32_t l = lane(), lr = l & 15u;
-    run_sum_step<0x111, 0xf>(a, b, r >= 1u);
-    run_sum_step<0x112, 0xf>(a, b, r >= 2u);
-    run_sum_step<0x114, 0xf>(a, b, r >= 4u);
-    run_sum_step<0x118, 0xf>(a, b, r >= 8u);
-    run_sum_step<0x142, 0xa>(a, b, (l & 16u) != 0u && r > lr);
-    run_sum_step<0x143, 0xc>(a, b, l >= 32u && r + 32u > l);
-}
-
 template <int Ctrl, int RowMask>
-__device__ __forceinline__ void run_sum_step3(uint32_t& a, uint32_t& b, uint32_t& c, bool t) {
-    const uint32_t ya = dpp_in<Ctrl, RowMask>(a), yb = dpp_in<Ctrl, RowMask>(b);
-    const uint32_t yc = dpp_in<Ctrl, RowMask>(c);
-    add_if(a, ya, t);
-    add_if(b, yb, t);
-    add_if(c, yc, t);
+__device__ __forceinline__ void run_sum_step(float& a, bool c) {
+    const float y = __uint_as_float(dpp_in<Ctrl, RowMask>(__float_as_uint(a)));
+    a = c ? a + y : a;
 }
 
-// run_sums over three integer values
-__device__ __forceinline__ void run_sums3(uint32_t& a, uint32_t& b, uint32_t& c, uint32_t r) {
+// (tree order: the noise sums of the cluster threshold)
+__device__ __forceinline__ void run_sums(float& a, uint32_t r) {
     const uint32_t l = lane(), lr = l & 15u;
-    run_sum_step3<0x111, 0xf>(a, b, c, r >= 1u);
-    run_sum_step3<0x112, 0xf>(a, b, c, r >= 2u);
-    run_sum_step3<0x114, 0xf>(a, b, c, r >= 4u);
-    run_sum_step3<0x118, 0xf>(a, b, c, r >= 8u);
-    run_sum_step3<0x142, 0xa>(a, b, c, (l & 16u) != 0u && r > lr);
-    run_sum_step3<0x143, 0xc>(a, b, c, l >= 32u && r + 32u > l);
+    run_sum_step<0x111, 0xf>(a, r >= 1u);
+    run_sum_step<0x112, 0xf>(a, r >= 2u);
+    run_sum_step<0x114, 0xf>(a, r >= 4u);
+    run_sum_step<0x118, 0xf>(a, r >= 8u);
+    run_sum_step<0x142, 0xa>(a, (l & 16u) != 0u && r > lr);
+    run_sum_step<0x143, 0xc>(a, l >= 32u && r + 32u > l);
 }
 
 // Inclusive sum over the wavefront in six DPP steps: row_shr 1, 2, 4, 8 inside rows of 16 lanes,
@@ -152,6 +123,27 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     x += dpp_in<0x142, 0xa>(x);
     x += dpp_in<0x143, 0xc>(x);
     return x;
+}
+
+// run_sums for integers, exactly (modulo 2^32, so exact wherever a run's true sum is below
+// 2^32): the plain inclusive scan minus its value at the lane just below the run's first lane
+// (read with ds_bpermute; 0 when the run starts at lane 0).
+__device__ __forceinline__ uint32_t scan_below(uint32_t p, uint32_t first) {
+    const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((first - 1u) << 2), (int)p);
+    return first ? y : 0u;
+}
+__device__ __forceinline__ void run_sums_int(uint32_t& a, uint32_t& b, uint32_t r) {
+    const uint32_t first = lane() - r;
+    const uint32_t pa = wave_incl_scan(a), pb = wave_incl_scan(b);
+    a = pa - scan_below(pa, first);
+    b = pb - scan_below(pb, first);
+}
+__device__ __forceinline__ void run_sums_int3(uint32_t& a, uint32_t& b, uint32_t& c, uint32_t r) {
+    const uint32_t first = lane() - r;
+    const uint32_t pa = wave_incl_scan(a), pb = wave_incl_scan(b), pc = wave_incl_scan(c);
+    a = pa - scan_below(pa, first);
+    b = pb - scan_below(pb, first);
+    c = pc - scan_below(pc, first);
 }
 
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t& total) {
@@ -327,28 +319,37 @@ __device__ WalkResult stage_and_walk(TileSmem<W, DW>& sm, const uint8_t* g, uint
             // the walk is a serial chain that the tile's other waves wait for at the next
             // barrier: its wave issues ahead of the CU's other waves meanwhile
             __builtin_amdgcn_s_setprio(3);
-            // lane k (mod 64) keeps channel k's record position and length. Branch-free steps
-            // whose serial chain is only read, add, clamp: a record fits the FED when the next
-            // position is <= L, and since positions only grow, the records that fit come first
-            // (past the first one that does not, the reads stay inside the stage and are unused).
+            // lane k (mod 64) keeps channel k's payload position. Branch-free steps whose
+            // serial chain is only read, add, clamp. Record k ends where record k + 1's length
+            // field starts, so the lengths and the fit test come from the positions afterwards:
+            // a record fits the FED when its end is <= L, and since ends only grow, the records
+            // that fit come first (past the first one that does not, the reads stay inside the
+            // stage and are unused). Ends stay below 2^23 (96 x (2 + 65535)): no sum wraps.
             constexpr uint32_t omax = TileSmem<W, DW>::kStageBytes - 2;
-            uint32_t pos = 0, good = 0;
-            uint32_t vpos0 = 0, vpos1 = 0, vlen0 = 0, vlen1 = 0;
-            auto step = [&](uint32_t k, uint32_t& vpos, uint32_t& vlen) {
+            uint32_t pos = 0;
+            uint32_t vpos0 = 0, vpos1 = 0;
+            auto step = [&](uint32_t k, uint32_t& vpos) {
                 uint32_t o = pos + delta;
                 o = o < omax ? o : omax;
                 const uint32_t P = uni(lds_u16(sm.stage, o));
-                const uint32_t nxt = pos + 2u + P;
-                good += nxt <= L ? 1u : 0u;
-                const bool mine = lane() == (k & 63u);
-                vpos = mine ? pos + 2 : vpos;
-                vlen = mine ? P : vlen;
-                pos = nxt;
+                vpos = __builtin_amdgcn_inverse_ballot_w64(1ull << (k & 63u)) ? pos + 2u : vpos;
+                pos += 2u + P;
             };
 #pragma unroll 8
-            for (uint32_t k = 0; k < 64u; ++k) step(k, vpos0, vlen0);
+            for (uint32_t k = 0; k < 64u; ++k) step(k, vpos0);
 #pragma unroll 8
-            for (uint32_t k = 64; k < (uint32_t)kNch; ++k) step(k, vpos1, vlen1);
+            for (uint32_t k = 64; k < (uint32_t)kNch; ++k) step(k, vpos1);
+            constexpr uint32_t kLast = (uint32_t)kNch - 65u;   // lane of channel 95 in vpos1
+            const uint32_t l = lane();
+            // (the cross-lane reads are taken by every lane first: inside a conditional
+            // expression they would run under a partial exec mask, and a DPP read from a
+            // disabled lane returns the fallback value)
+            const uint32_t next1 = (uint32_t)__builtin_amdgcn_readlane((int)vpos1, 0);
+            const uint32_t nx0 = from_next_lane(vpos0), nx1 = from_next_lane(vpos1);
+            const uint32_t end0 = (l == 63u ? next1 : nx0) - 2u;
+            const uint32_t end1 = l == kLast ? pos : nx1 - 2u;
+            const uint32_t vlen0 = end0 - vpos0, vlen1 = end1 - vpos1;
+            const uint32_t good = popc(__ballot(end0 <= L)) + popc(__ballot(l <= kLast && end1 <= L));
             sm.ch_pos[lane()] = vpos0;
             sm.ch_len[lane()] = (uint16_t)vlen0;
             sm.ch_pos[64 + lane()] = vpos1;   // entries 96..127 are never read
@@ -760,7 +761,11 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
     }
     SB = contB ? SB + SA : SB;
     QB = contB ? QB + QA : QB;
-    run_sums(SB, QB, pr.lanes);
+    run_sums(SB, pr.lanes);
+    {
+        const uint32_t pq = wave_incl_scan(QB);
+        QB = pq - scan_below(pq, l - pr.lanes);
+    }
     {
         const float Sp = __uint_as_float(from_prev_lane(__float_as_uint(SB)));
         const uint32_t Qp = from_prev_lane(QB);
@@ -848,8 +853,8 @@ __device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const Devic
 // ---- outputs ------------------------------------------------------------------------------
 // Uniform state of the member run still open at the last digi of the previous write step.
 struct OpenCluster {
-    uint32_t open;   // 1: the last digi of the previous step was a member
-    uint32_t acc;    // acceptance of that digi's run (for the digis that continue it)
+    uint32_t open;   // 1: the last digi of the previous step was a member (so its run, which
+                     // the digis that continue it share, was accepted)
     uint32_t rp;     // run position of that digi
     uint32_t C, M;   // sums of c and strip*c so far (module rows: of the low 16 bits of pos*c)
     uint32_t Mh;     // module rows: sum of the high bits of pos*c
@@ -899,53 +904,54 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
     constexpr uint32_t kStep = 2 * kWave;
     gmut<uint16_t>* adc_out = gm(ev.adc);
     gmut<u32x4>* cl_out = gm(reinterpret_cast<u32x4*>(ev.cl));
-    OpenCluster oc{0u, 0u, 0u, 0u, 0u, 0u, u32x4{0u, 0u, 0u, 0u}};
+    OpenCluster oc{0u, 0u, 0u, 0u, 0u, u32x4{0u, 0u, 0u, 0u}};
     uint32_t rc = base_cl, pa = base_adc;
     const uint32_t l = lane();
     // the digi words and APV gains of the next step are read while this step runs
     auto gain_of = [&](uint32_t d) { return sm.gain[2 * d_ch(d) + (d_strip(d) >> 7)]; };
+    // (the index is clamped so that the read stays inside the list; digis past nd read as 0)
     auto load = [&](uint32_t j, uint32_t& dA, uint32_t& dB) {
-        u32x2 w = {0u, 0u};
-        if (j < nd) w = *reinterpret_cast<const u32x2*>(dl + j);   // dl + j + 1 is inside the list
-        dA = w.x;
-        dB = j + 1u < nd ? w.y : 0u;
+        const u32x2 w = *reinterpret_cast<const u32x2*>(dl + (j < nd ? j : 0u));
+        dA = j < nd ? w.x : 0u;
+        dB = j + 1u < nd ? w.y : 0u;   // j even, nd <= the list's even length: dl + j + 1 is inside
     };
     uint32_t nA, nB;
     load(2u * l, nA, nB);
     float gnA = gain_of(nA), gnB = gain_of(nB);
+    // Straight-line steps: every value of a step is formed first and the stores come last, so
+    // that no lane mask has to live across a branch.
     for (uint32_t base = 0; base < nd; base += kStep) {
         const uint32_t dA = nA, dB = nB;
         const float gA = gnA, gB = gnB;
         load(base + kStep + 2u * l, nA, nB);
+        gnA = gain_of(nA);
+        gnB = gain_of(nB);
         const bool actA = (dA & kActBit) != 0u, actB = (dB & kActBit) != 0u;
         const bool contA = (dA & kContBit) != 0u, contB = (dB & kContBit) != 0u;
         const bool cont0 = (__ballot(contA) & 1ull) != 0ull;
-        // the cluster open at the end of the previous step is complete unless lane 0 continues it
-        if (oc.open && !cont0) {
-            if (rc < ev.cap_cl) cl_out[rc] = oc.rec;   // same record from every lane
-            rc += 1;
-        }
+        // the cluster open at the end of the previous step is complete unless lane 0 continues
+        // it: its record goes first
+        const bool pend = oc.open != 0u && !cont0;
+        const uint32_t rc_pend = rc;
+        const u32x4 rec_pend = oc.rec;
+        rc += pend ? 1u : 0u;
         const PairRuns pr = pair_runs(actA, contA, actB, contB, cont0, oc.rp + 1u);
         const uint32_t rpA = pr.rpA, rpB = pr.rpB;
         // members: active digis whose run head carries the accepted bit; the head of A's run
         // sits rpA positions back (in an earlier step when fromA)
-        const uint64_t abA = __ballot(actA && !contA && (dA & kAccBit));
-        const uint64_t abB = __ballot(actB && !contB && (dB & kAccBit));
+        const uint64_t abA = __ballot((dA & (kActBit | kContBit | kAccBit)) == (kActBit | kAccBit));
+        const uint64_t abB = __ballot((dB & (kActBit | kContBit | kAccBit)) == (kActBit | kAccBit));
         const uint32_t headA = 2u * l - (actA ? rpA : 0u);
-        const bool accA = pr.fromA ? (oc.acc != 0u)
-                                   : ((((headA & 1u) ? abB : abA) >> (headA >> 1)) & 1ull) != 0ull;
+        const uint32_t bitA = (uint32_t)(((headA & 1u) ? abB : abA) >> (headA >> 1)) & 1u;
+        const bool accA = (pr.fromA ? oc.open : bitA) != 0u;
         const bool memA = actA && accA;
         const bool memB = actB && (contB ? accA : ((abB >> l) & 1ull) != 0ull);
-        uint32_t cA = 0, cB = 0;
-        if (memA) cA = corrected_adc(dA, gA);
-        if (memB) cB = corrected_adc(dB, gB);
+        // every lane divides (no branch): non-members take 0
+        const uint32_t qA = corrected_adc(dA, gA), qB = corrected_adc(dB, gB);
+        const uint32_t cA = memA ? qA : 0u, cB = memB ? qB : 0u;
         const uint64_t mbA = __ballot(memA), mbB = __ballot(memB);
-        {
-            const uint32_t p = pa + popc(mbA & mask_lt()) + popc(mbB & mask_lt());
-            if (memA && p < ev.cap_adc) adc_out[p] = (uint16_t)cA;
-            const uint32_t q = p + (memA ? 1u : 0u);
-            if (memB && q < ev.cap_adc) adc_out[q] = (uint16_t)cB;
-        }
+        const uint32_t padc = pa + popc(mbA & mask_lt()) + popc(mbB & mask_lt());
+        const uint32_t padcB = padc + (memA ? 1u : 0u);
         pa += popc(mbA) + popc(mbB);
         // charge and strip-weighted charge along member runs: each lane's share of the run of
         // its digi B is summed across lanes; digi A takes the previous lane's total
@@ -970,9 +976,9 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         MB += contB ? MA : 0u;
         if constexpr (kMod) {
             MhB += contB ? MhA : 0u;
-            run_sums3(CB, MB, MhB, pr.lanes);
+            run_sums_int3(CB, MB, MhB, pr.lanes);
         } else {
-            run_sums(CB, MB, pr.lanes);
+            run_sums_int(CB, MB, pr.lanes);
         }
         {
             const uint32_t Cp = from_prev_lane(CB), Mp = from_prev_lane(MB);
@@ -991,34 +997,26 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         const bool endA = memA && !contB;
         const bool endB = memB && !next_contA;
         const bool eB = endB && l != 63u;
-        // one record per lane first (A's where A ends, else B's), B's too where both end
-        u32x4 rec1 = {0u, 0u, 0u, 0u}, recB = {0u, 0u, 0u, 0u};
-        if (endA || endB) {
-            rec1 = make_record<kMod>(fed, endA ? dA : dB, endA ? rpA : rpB, endA ? CA : CB,
-                                     endA ? MA : MB, endA ? MhA : MhB);
-        }
-        const bool both = endA && endB;
-        if (__ballot(both) != 0ull) {
-            if (both) recB = make_record<kMod>(fed, dB, rpB, CB, MB, MhB);
-        }
-        if (!endA) recB = rec1;
+        // (every lane forms both: the divisions run for the whole wavefront in any case)
+        const u32x4 rec1 = make_record<kMod>(fed, endA ? dA : dB, endA ? rpA : rpB,
+                                             endA ? CA : CB, endA ? MA : MB, endA ? MhA : MhB);
+        const u32x4 recB = endA ? make_record<kMod>(fed, dB, rpB, CB, MB, MhB) : rec1;
         const uint64_t ebA = __ballot(endA), ebB = __ballot(eB);
-        {
-            const uint32_t p = rc + popc(ebA & mask_lt()) + popc(ebB & mask_lt());
-            if (endA && p < ev.cap_cl) cl_out[p] = rec1;
-            const uint32_t q = p + (endA ? 1u : 0u);
-            if (eB && q < ev.cap_cl) cl_out[q] = recB;
-        }
+        const uint32_t prec = rc + popc(ebA & mask_lt()) + popc(ebB & mask_lt());
+        const uint32_t precB = prec + (endA ? 1u : 0u);
         rc += popc(ebA) + popc(ebB);
         oc.open = (uint32_t)(mbB >> 63);
-        oc.acc = (uint32_t)((__ballot(memB) >> 63) & 1ull);
         oc.rp = last_lane(rpB);
         oc.C = last_lane(CB);
         oc.M = last_lane(MB);
         if constexpr (kMod) oc.Mh = last_lane(MhB);
         oc.rec = u32x4{last_lane(recB.x), last_lane(recB.y), last_lane(recB.z), last_lane(recB.w)};
-        gnA = gain_of(nA);
-        gnB = gain_of(nB);
+        // stores (the pending record: the same value from every lane)
+        if (pend && rc_pend < ev.cap_cl) cl_out[rc_pend] = rec_pend;
+        if (memA && padc < ev.cap_adc) adc_out[padc] = (uint16_t)cA;
+        if (memB && padcB < ev.cap_adc) adc_out[padcB] = (uint16_t)cB;
+        if (endA && prec < ev.cap_cl) cl_out[prec] = rec1;
+        if (eB && precB < ev.cap_cl) cl_out[precB] = recB;
     }
     if (oc.open && rc < ev.cap_cl) cl_out[rc] = oc.rec;
     wave_sync();
