@@ -125,6 +125,17 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     return x;
 }
 
+// Inclusive maximum over the wavefront, in the same six DPP steps (out-of-row sources read 0).
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
+    x = __builtin_elementwise_max(x, dpp_in<0x111, 0xf>(x));
+    x = __builtin_elementwise_max(x, dpp_in<0x112, 0xf>(x));
+    x = __builtin_elementwise_max(x, dpp_in<0x114, 0xf>(x));
+    x = __builtin_elementwise_max(x, dpp_in<0x118, 0xf>(x));
+    x = __builtin_elementwise_max(x, dpp_in<0x142, 0xa>(x));
+    x = __builtin_elementwise_max(x, dpp_in<0x143, 0xc>(x));
+    return x;
+}
+
 // run_sums for integers, exactly (modulo 2^32, so exact wherever a run's true sum is below
 // 2^32): the plain inclusive scan minus its value at the lane just below the run's first lane
 // (read with ds_bpermute; 0 when the run starts at lane 0).
@@ -676,30 +687,39 @@ __device__ void settle_runs(uint32_t* dl, uint32_t nd, gconst<float>* noise, flo
 // Runs of a step of 128 digis, two per lane: digi A of lane l sits at position 2l, B at 2l + 1.
 // Digi A of lane 0 heads the part of its run that lies in the step. Run positions count from the
 // run's first digi, across steps too (carry: run position + 1 of the previous step's last digi).
+// Each head may carry a tag bit (tagA, tagB: read only where the digi heads its part of a run),
+// which every digi of the part learns.
 struct PairRuns {
     uint32_t rpA, rpB;   // run positions of A and B
     bool fromA;          // A's run began in an earlier step
     uint32_t lanes;      // lanes back to where the run of B starts (0 when B is inactive)
+    bool tagA, tagB;     // the tags of the heads of A's and B's runs (where active)
 };
 __device__ __forceinline__ PairRuns pair_runs(bool actA, bool contA, bool actB, bool contB,
-                                              bool cont0, uint32_t carry) {
+                                              bool cont0, uint32_t carry, bool tagA = false,
+                                              bool tagB = false) {
     const uint32_t l = lane();
     const bool hA = actA && (!contA || l == 0u);
     const bool hB = actB && !contB;
-    // nearest head at or below A: heads A of lanes <= l (position 2j), heads B of lanes < l (2j+1)
-    const uint64_t ha = __ballot(hA) & mask_le(), hb = __ballot(hB) & mask_lt();
-    const uint32_t qa = ha ? 2u * (63u - (uint32_t)__clzll((long long)ha)) + 1u : 0u;
-    const uint32_t qb = hb ? 2u * (63u - (uint32_t)__clzll((long long)hb)) + 2u : 0u;
-    const uint32_t headA = (qa > qb ? qa : qb) - 1u;
+    // 2 (1 + the position of the last head at or below each lane's digi B) + that head's tag
+    // (0: none), by a running maximum over the lanes; A's is this lane's A if it heads a run,
+    // else the previous lane's
+    const uint32_t ownA = (2u * l + 1u) * 2u + (tagA ? 1u : 0u);
+    const uint32_t own = hB ? (2u * l + 2u) * 2u + (tagB ? 1u : 0u) : hA ? ownA : 0u;
+    const uint32_t upto_b = wave_incl_max(own);
+    const uint32_t before = from_prev_lane(upto_b);
+    const uint32_t atA = hA ? ownA : before;
+    const uint32_t headA = (atA >> 1) - 1u;
     const uint32_t lrpA = actA ? 2u * l - headA : 0u;
     const uint32_t lrpB = contB ? lrpA + 1u : 0u;
     PairRuns r;
     r.fromA = actA && cont0 && headA == 0u;
     r.rpA = lrpA + (r.fromA ? carry : 0u);
     r.rpB = lrpB + ((contB && r.fromA) ? carry : 0u);
-    // the run of B starts in lane l when B heads it or continues an A that heads it
-    const uint64_t sb = __ballot(hB || (contB && hA)) & mask_le();
-    r.lanes = actB ? l - (sb ? 63u - (uint32_t)__clzll((long long)sb) : 0u) : 0u;
+    // the run of an active B starts in the lane of the last head at or below B
+    r.lanes = actB ? l - (((upto_b >> 1) - 1u) >> 1) : 0u;
+    r.tagA = (atA & 1u) != 0u;
+    r.tagB = (upto_b & 1u) != 0u;
     return r;
 }
 
@@ -858,7 +878,6 @@ struct OpenCluster {
     uint32_t rp;     // run position of that digi
     uint32_t C, M;   // sums of c and strip*c so far (module rows: of the low 16 bits of pos*c)
     uint32_t Mh;     // module rows: sum of the high bits of pos*c
-    u32x4 rec;       // its record as it stands (valid if the cluster ends there)
 };
 
 // Record of the cluster whose last digi is dw, rp positions after its first. Channel runs: M is
@@ -882,9 +901,11 @@ __device__ __forceinline__ u32x4 make_record(uint32_t fed, uint32_t dw, uint32_t
         m = (double)M;
     }
     const uint32_t width = rp + 1u;
-    // barycenter: sum (s+1/2) c / sum c = (2M + C) / (2C), numerator and denominator exact
-    const float bary = C ? (float)((2.0 * m + (double)C) / (2.0 * (double)C))
-                         : (float)first + (float)width * 0.5f;
+    // barycenter: sum (s+1/2) c / sum c = (2M + C) / (2C), numerator and denominator exact (both
+    // forms are computed, the quotient is NaN when C = 0, so that no branch splits the step)
+    const float q = (float)((2.0 * m + (double)C) / (2.0 * (double)C));
+    const float mid = (float)first + (float)width * 0.5f;
+    const float bary = C ? q : mid;
     return u32x4{fed * kNch + ch, first | (width << 16), C, __float_as_uint(bary)};
 }
 
@@ -904,7 +925,7 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
     constexpr uint32_t kStep = 2 * kWave;
     gmut<uint16_t>* adc_out = gm(ev.adc);
     gmut<u32x4>* cl_out = gm(reinterpret_cast<u32x4*>(ev.cl));
-    OpenCluster oc{0u, 0u, 0u, 0u, 0u, u32x4{0u, 0u, 0u, 0u}};
+    OpenCluster oc{0u, 0u, 0u, 0u, 0u};
     uint32_t rc = base_cl, pa = base_adc;
     const uint32_t l = lane();
     // the digi words and APV gains of the next step are read while this step runs
@@ -930,22 +951,17 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         const bool contA = (dA & kContBit) != 0u, contB = (dB & kContBit) != 0u;
         const bool cont0 = (__ballot(contA) & 1ull) != 0ull;
         // the cluster open at the end of the previous step is complete unless lane 0 continues
-        // it: its record goes first
-        const bool pend = oc.open != 0u && !cont0;
-        const uint32_t rc_pend = rc;
-        const u32x4 rec_pend = oc.rec;
-        rc += pend ? 1u : 0u;
-        const PairRuns pr = pair_runs(actA, contA, actB, contB, cont0, oc.rp + 1u);
+        // it: its record, already in its slot, is counted
+        rc += (oc.open != 0u && !cont0) ? 1u : 0u;
+        // members: active digis whose run head carries the accepted bit. The heads tag their
+        // runs with it; lane 0's A, when it continues a run of the previous step, tags with that
+        // run's acceptance (a member ended that step).
+        const bool tA = (dA & kAccBit) != 0u || (l == 0u && contA && oc.open != 0u);
+        const bool tB = (dB & kAccBit) != 0u;
+        const PairRuns pr = pair_runs(actA, contA, actB, contB, cont0, oc.rp + 1u, tA, tB);
         const uint32_t rpA = pr.rpA, rpB = pr.rpB;
-        // members: active digis whose run head carries the accepted bit; the head of A's run
-        // sits rpA positions back (in an earlier step when fromA)
-        const uint64_t abA = __ballot((dA & (kActBit | kContBit | kAccBit)) == (kActBit | kAccBit));
-        const uint64_t abB = __ballot((dB & (kActBit | kContBit | kAccBit)) == (kActBit | kAccBit));
-        const uint32_t headA = 2u * l - (actA ? rpA : 0u);
-        const uint32_t bitA = (uint32_t)(((headA & 1u) ? abB : abA) >> (headA >> 1)) & 1u;
-        const bool accA = (pr.fromA ? oc.open : bitA) != 0u;
-        const bool memA = actA && accA;
-        const bool memB = actB && (contB ? accA : ((abB >> l) & 1ull) != 0ull);
+        const bool memA = actA && pr.tagA;
+        const bool memB = actB && pr.tagB;
         // every lane divides (no branch): non-members take 0
         const uint32_t qA = corrected_adc(dA, gA), qB = corrected_adc(dB, gB);
         const uint32_t cA = memA ? qA : 0u, cB = memB ? qB : 0u;
@@ -1000,7 +1016,8 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         // (every lane forms both: the divisions run for the whole wavefront in any case)
         const u32x4 rec1 = make_record<kMod>(fed, endA ? dA : dB, endA ? rpA : rpB,
                                              endA ? CA : CB, endA ? MA : MB, endA ? MhA : MhB);
-        const u32x4 recB = endA ? make_record<kMod>(fed, dB, rpB, CB, MB, MhB) : rec1;
+        const u32x4 rec2 = make_record<kMod>(fed, dB, rpB, CB, MB, MhB);
+        const u32x4 recB = endA ? rec2 : rec1;
         const uint64_t ebA = __ballot(endA), ebB = __ballot(eB);
         const uint32_t prec = rc + popc(ebA & mask_lt()) + popc(ebB & mask_lt());
         const uint32_t precB = prec + (endA ? 1u : 0u);
@@ -1010,15 +1027,14 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         oc.C = last_lane(CB);
         oc.M = last_lane(MB);
         if constexpr (kMod) oc.Mh = last_lane(MhB);
-        oc.rec = u32x4{last_lane(recB.x), last_lane(recB.y), last_lane(recB.z), last_lane(recB.w)};
-        // stores (the pending record: the same value from every lane)
-        if (pend && rc_pend < ev.cap_cl) cl_out[rc_pend] = rec_pend;
+        // stores. The cluster open at digi B of lane 63 takes the next slot: its record as it
+        // stands goes there now, and a step that extends the cluster stores it there again.
         if (memA && padc < ev.cap_adc) adc_out[padc] = (uint16_t)cA;
         if (memB && padcB < ev.cap_adc) adc_out[padcB] = (uint16_t)cB;
         if (endA && prec < ev.cap_cl) cl_out[prec] = rec1;
         if (eB && precB < ev.cap_cl) cl_out[precB] = recB;
+        if (memB && l == 63u && rc < ev.cap_cl) cl_out[rc] = recB;
     }
-    if (oc.open && rc < ev.cap_cl) cl_out[rc] = oc.rec;
     wave_sync();
 }
 
