@@ -62,8 +62,10 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // 16-byte global 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));   // two digi words
 
 __device__ __forceinline__ uint32_t lane() { return __lane_id(); }
-__device__ __forceinline__ uint64_t mask_lt() { return (1ull << lane()) - 1ull; }
-__device__ __forceinline__ uint64_t mask_le() { return mask_lt() | (1ull << lane()); }
+// x + the set bits of the wave mask m below this lane (v_mbcnt)
+__device__ __forceinline__ uint32_t count_below(uint64_t m, uint32_t x) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, x));
+}
 __device__ __forceinline__ uint32_t popc(uint64_t m) { return (uint32_t)__popcll(m); }
 __device__ __forceinline__ uint32_t uni(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
@@ -803,8 +805,9 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
     const uint32_t markA = cluster_mark<kMod>(endA, rpA, QA, SA, cal.t_cluster);
     const uint32_t markB = cluster_mark<kMod>(endB, rpB, QB, SB, cal.t_cluster);
     const bool eB = markB != 0u && l != 63u;
-    if (markA) dl[jA - rpA] |= markA;
-    if (eB) dl[jB - rpB] |= markB;
+    // (LDS atomic ORs: no read back; each run has one end, so the words differ)
+    if (markA) __hip_atomic_fetch_or(&dl[jA - rpA], markA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if (eB) __hip_atomic_fetch_or(&dl[jB - rpB], markB, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     const bool accA = markA == kAccBit, accB = eB && markB == kAccBit;
     my_adc += (accA ? rpA + 1u : 0u) + (accB ? rpB + 1u : 0u);
     n_cl += popc(__ballot(accA)) + popc(__ballot(accB));
@@ -966,7 +969,7 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         const uint32_t qA = corrected_adc(dA, gA), qB = corrected_adc(dB, gB);
         const uint32_t cA = memA ? qA : 0u, cB = memB ? qB : 0u;
         const uint64_t mbA = __ballot(memA), mbB = __ballot(memB);
-        const uint32_t padc = pa + popc(mbA & mask_lt()) + popc(mbB & mask_lt());
+        const uint32_t padc = count_below(mbB, count_below(mbA, pa));
         const uint32_t padcB = padc + (memA ? 1u : 0u);
         pa += popc(mbA) + popc(mbB);
         // charge and strip-weighted charge along member runs: each lane's share of the run of
@@ -1019,7 +1022,7 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint
         const u32x4 rec2 = make_record<kMod>(fed, dB, rpB, CB, MB, MhB);
         const u32x4 recB = endA ? rec2 : rec1;
         const uint64_t ebA = __ballot(endA), ebB = __ballot(eB);
-        const uint32_t prec = rc + popc(ebA & mask_lt()) + popc(ebB & mask_lt());
+        const uint32_t prec = count_below(ebB, count_below(ebA, rc));
         const uint32_t precB = prec + (endA ? 1u : 0u);
         rc += popc(ebA) + popc(ebB);
         oc.open = (uint32_t)(mbB >> 63);
