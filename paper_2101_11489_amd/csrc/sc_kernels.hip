@@ -194,10 +194,10 @@ __device__ __forceinline__ unsigned long long pack_state(uint64_t flag, uint32_t
 }
 
 // Digi word in the list: adc(8) | strip(8) | channel-in-FED(7), and after forming the flags
-// active | seed | continues-previous | accepted | undecided (the last two on the first digi of a
-// run: accepted, or left to the sequential noise sum).
-constexpr uint32_t kActBit = 1u << 23, kSeedBit = 1u << 24, kContBit = 1u << 25,
-                   kAccBit = 1u << 26, kRedoBit = 1u << 27;
+// active | continues-previous | accepted | undecided (the last two on the first digi of a run:
+// accepted, or left to the sequential noise sum). Seeds are counted while forming, not kept.
+constexpr uint32_t kActBit = 1u << 23, kContBit = 1u << 25, kAccBit = 1u << 26,
+                   kRedoBit = 1u << 27;
 constexpr uint32_t kNoKey = 0xffffffffu;
 __device__ __forceinline__ uint32_t d_adc(uint32_t d) { return d & 255u; }
 __device__ __forceinline__ uint32_t d_strip(uint32_t d) { return (d >> 8) & 255u; }
@@ -641,19 +641,21 @@ struct OpenRun {
 // most 768 (a path through the tree has at most about 10 roundings per 128-digi step, and such
 // runs span at most 3 and 7 steps); the sequential sum is within L (L = rp + 1 strips). Half of
 // that in the square root plus the roundings of the root and the product stay below
-// e = (L + 64) * 2^-24, so wherever q >= r (1 + e) or q < r (1 - e), r = t * sqrt(St), the
-// sequential sum decides the same way. Returns the head bit: kAccBit (accepted), kRedoBit (too
-// close to call: settle_runs decides from the sequential sum) or 0.
+// e = (L + 64) * 2^-24 by more than 2 roundings, so wherever q - r >= r e or q - r < -r e,
+// r = t * sqrt(St) (the difference and r e each rounded once), the sequential sum decides the
+// same way. Returns the head bit: kAccBit (accepted), kRedoBit (too close to call: settle_runs
+// decides from the sequential sum) or 0.
 template <bool kMod>
 __device__ __forceinline__ uint32_t cluster_mark(bool end, uint32_t rp, uint32_t Q, float St,
                                                  float t) {
     const bool seeded = end && (Q >> kQShift<kMod>) != 0u;
     const float q = (float)(Q & ((1u << kQShift<kMod>) - 1u));
     const float r = t * __builtin_amdgcn_sqrtf(St);
-    const float e = (float)(rp + 65u) * 0x1p-24f;
+    const float re = r * ((float)(rp + 65u) * 0x1p-24f);   // (L + 64) fits a float exactly
+    const float d = q - r;
     const bool in_range = St >= 0x1p-60f && St <= 0x1p100f;   // false for NaN
-    const bool yes = in_range && q >= r * (1.0f + e);
-    const bool no = in_range && q < r * (1.0f - e);
+    const bool yes = in_range && d >= re;
+    const bool no = in_range && d < -re;
     return !seeded ? 0u : yes ? kAccBit : no ? 0u : kRedoBit;
 }
 
@@ -795,8 +797,8 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
         SA = in ? SA + Sp : SA;
         QA = in ? QA + Qp : QA;
     }
-    if (vA) dl[jA] = dA | (actA ? kActBit : 0u) | (sdA ? kSeedBit : 0u) | (contA ? kContBit : 0u);
-    if (vB) dl[jB] = dB | (actB ? kActBit : 0u) | (sdB ? kSeedBit : 0u) | (contB ? kContBit : 0u);
+    if (vA) dl[jA] = dA | (actA ? kActBit : 0u) | (contA ? kContBit : 0u);
+    if (vB) dl[jB] = dB | (actB ? kActBit : 0u) | (contB ? kContBit : 0u);
     // runs that end inside this step; the run at digi B of lane 63 may go on, so it stays open
     // with its threshold decision as it stands
     const bool next_contA = from_next_lane(contA ? 1u : 0u) != 0u;
@@ -833,19 +835,20 @@ __device__ __forceinline__ void form_pass(uint32_t* dl, uint32_t nd, const Devic
     for (uint32_t b = 0; b < nd; b += kBatch * kStep) {
         uint32_t dA[kBatch], dB[kBatch];
         float nA[kBatch], nB[kBatch];
+        // every lane loads (no branch): past nd the index is clamped and the digi reads as 0, whose
+        // noise load (strip 0 of the FED) is unused
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
             const uint32_t j = b + (uint32_t)k * kStep + 2u * lane();
-            u32x2 w = {0u, 0u};
-            if (j < nd) w = *reinterpret_cast<const u32x2*>(dl + j);   // dl + j + 1 is inside the list
-            dA[k] = w.x;
+            // j even, nd <= the list's even length: dl + j + 1 is inside the list
+            const u32x2 w = *reinterpret_cast<const u32x2*>(dl + (j < nd ? j : 0u));
+            dA[k] = j < nd ? w.x : 0u;
             dB[k] = j + 1u < nd ? w.y : 0u;
         }
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
-            const uint32_t j = b + (uint32_t)k * kStep + 2u * lane();
-            nA[k] = j < nd ? noise[d_pos(dA[k])] : 0.0f;
-            nB[k] = j + 1u < nd ? noise[d_pos(dB[k])] : 0.0f;
+            nA[k] = noise[d_pos(dA[k])];
+            nB[k] = noise[d_pos(dB[k])];
         }
 #pragma unroll
         for (int k = 0; k < kBatch; ++k) {
