@@ -886,6 +886,21 @@ struct OpenCluster {
     uint32_t Mh;     // module rows: sum of the high bits of pos*c
 };
 
+// The float nearest to N / D for integers 0 <= N < 2^53 and 0 < D < 2^27, the same float as
+// (float)(N / D) with the double quotient: the reciprocal estimate and one Newton step give y
+// within 2^-40 of 1/D; the remainder r = N - D q1 of q1 = N y is exact (a multiple of ulp(q1),
+// fewer than 2^28 of them), and q2 = q1 + r y lies within 2^-53 (1 + 2^-40) relative of N / D.
+// A quotient that is not a float midpoint lies at least 2^-25 / D > 2^-52 relative from one (it
+// differs from it by a multiple of the midpoint's last bit over D), so q2 rounds to the same
+// float; a midpoint is a double, and q2 is that double.
+__device__ __forceinline__ float quotient_to_float(double N, double D) {
+    const double y0 = __builtin_amdgcn_rcp(D);
+    const double y = __builtin_fma(y0, __builtin_fma(-D, y0, 1.0), y0);
+    const double q1 = N * y;
+    const double r = __builtin_fma(-D, q1, N);
+    return (float)__builtin_fma(r, y, q1);
+}
+
 // Record of the cluster whose last digi is dw, rp positions after its first. Channel runs: M is
 // the sum of strip * c. Module rows: the cluster may start in an earlier channel of the row, so
 // its channel and first strip come from the position of its first digi (d_pos(dw) - rp), and the
@@ -907,9 +922,10 @@ __device__ __forceinline__ u32x4 make_record(uint32_t fed, uint32_t dw, uint32_t
         m = (double)M;
     }
     const uint32_t width = rp + 1u;
-    // barycenter: sum (s+1/2) c / sum c = (2M + C) / (2C), numerator and denominator exact (both
-    // forms are computed, the quotient is NaN when C = 0, so that no branch splits the step)
-    const float q = (float)((2.0 * m + (double)C) / (2.0 * (double)C));
+    // barycenter: sum (s+1/2) c / sum c = (2M + C) / (2C), numerator and denominator exact
+    // integers (2C < 2^27: C <= 768 x 65535). Both forms are computed, the quotient is garbage
+    // when C = 0, so that no branch splits the step.
+    const float q = quotient_to_float(2.0 * m + (double)C, 2.0 * (double)C);
     const float mid = (float)first + (float)width * 0.5f;
     const float bary = C ? q : mid;
     return u32x4{fed * kNch + ch, first | (width << 16), C, __float_as_uint(bary)};
