@@ -25,6 +25,7 @@ import hashlib
 import json
 import multiprocessing as mp
 import os
+import re
 import statistics
 import sys
 import time
@@ -62,7 +63,13 @@ def algorithmic_bytes(events, counts, n_fed):
 
 
 def kernel_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """sha256[:16] of the kernel source's code: comments and white space removed, so that a
+    change of comments alone keeps committed counter runs valid."""
+    text = open(KERNEL_SRC).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    text = re.sub(r"\s+", "", text)
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def load_traffic(workload, tuning):

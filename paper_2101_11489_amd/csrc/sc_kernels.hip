@@ -138,9 +138,9 @@ __device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
     return x;
 }
 
-// run_sums for integers, exactly (modulo 2^32, so exact wherever a run's true sum is below
-// 2^32): the plain inclusive scan minus its value at the lane just below the run's first lane
-// (read with ds_bpermute; 0 when the run starts at lane 0).
+// run_sums for integers: the plain inclusive scan minus its value at the lane just below the
+// run's first lane (read with ds_bpermute; 0 when the run starts at lane 0). Modulo 2^32 these
+// are the conditional adds' sums exactly, so wherever a run's sum fits 32 bits they are equal.
 __device__ __forceinline__ uint32_t scan_below(uint32_t p, uint32_t first) {
     const uint32_t y = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((first - 1u) << 2), (int)p);
     return first ? y : 0u;
@@ -887,12 +887,13 @@ struct OpenCluster {
 };
 
 // The float nearest to N / D for integers 0 <= N < 2^53 and 0 < D < 2^27, the same float as
-// (float)(N / D) with the double quotient: the reciprocal estimate and one Newton step give y
-// within 2^-40 of 1/D; the remainder r = N - D q1 of q1 = N y is exact (a multiple of ulp(q1),
-// fewer than 2^28 of them), and q2 = q1 + r y lies within 2^-53 (1 + 2^-40) relative of N / D.
-// A quotient that is not a float midpoint lies at least 2^-25 / D > 2^-52 relative from one (it
-// differs from it by a multiple of the midpoint's last bit over D), so q2 rounds to the same
-// float; a midpoint is a double, and q2 is that double.
+// (float)(N / D) with the double quotient. One Newton step takes the hardware reciprocal
+// estimate (good to 2^-14 or better) to y within 2^-28 of 1/D. The remainder r = N - D q1 of
+// q1 = N y is exact (a multiple of ulp(q1), fewer than 2^28 of them), and q2 = q1 + r y =
+// N/D + (q1 - N/D)(1 - D y), rounded, lies within 2^-53 + 2^-55 relative of N / D. A quotient
+// that is not a float midpoint lies at least 2^-25 / D > 2^-52 relative from one (it differs
+// from it by a multiple of the midpoint's last bit over D), so q2 rounds to the same float; a
+// midpoint is a double, and q2 is that double.
 __device__ __forceinline__ float quotient_to_float(double N, double D) {
     const double y0 = __builtin_amdgcn_rcp(D);
     const double y = __builtin_fma(y0, __builtin_fma(-D, y0, 1.0), y0);
@@ -923,8 +924,8 @@ __device__ __forceinline__ u32x4 make_record(uint32_t fed, uint32_t dw, uint32_t
     }
     const uint32_t width = rp + 1u;
     // barycenter: sum (s+1/2) c / sum c = (2M + C) / (2C), numerator and denominator exact
-    // integers (2C < 2^27: C <= 768 x 65535). Both forms are computed, the quotient is garbage
-    // when C = 0, so that no branch splits the step.
+    // integers (2C < 2^27: C <= 768 x 65535). Both forms are computed, so that no branch splits
+    // the step; the quotient is not used when C = 0.
     const float q = quotient_to_float(2.0 * m + (double)C, 2.0 * (double)C);
     const float mid = (float)first + (float)width * 0.5f;
     const float bary = C ? q : mid;
