@@ -40,7 +40,9 @@ import fedgen  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_kernel_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2101_11489_amd", "csrc", "sc_kernels.hip")
-STAGE_BYTES = 6640   # FED bytes the kernel's LDS stage holds; larger FEDs take the slow path
+STAGE_BYTES_SMALL = 6656   # the tuning's default LDS stage (sc_tuning.stage_bytes)
+STAGE_SLACK = 16           # a stage of S bytes holds FEDs of up to S - 16 bytes; larger ones
+                           # are read from global memory
 
 
 def log(*a):
@@ -83,7 +85,8 @@ def load_traffic(workload, tuning):
         return None
     key = [tuning[k] for k in ("chunk_digis", "tile_waves", "tiles_per_cu", "fed_major")]
     for ent in t.get("entries", []):
-        if ent.get("workload") == workload and ent.get("tuning") == key:
+        if (ent.get("workload") == workload and ent.get("tuning") == key and
+                ent.get("stage_bytes", STAGE_BYTES_SMALL) == tuning.get("stage_bytes", STAGE_BYTES_SMALL)):
             return ent.get("hbm_bytes_per_launch")
     return None
 
@@ -354,8 +357,9 @@ def ingest_line(sc, torch, ctx, events, outs, batch, reps):
 def stress_line(sc, torch, stream, workers, tuning, cap_cl, cap_adc, steps):
     """The 256-event stress batch at full size: one launch with output capacities sized for the
     64-event batch (overflows are reported with the needed sizes), then the batch again with
-    those sizes, timed. The retry is checked against a launch with capacities that always
-    suffice; oracle parity of this distribution is the GPU tests'."""
+    those sizes, timed, with the headline's tuning and with the autotuner's pick for this
+    distribution. Both retries are checked against launches with capacities that always suffice
+    and against each other; oracle parity of this distribution is the GPU tests'."""
     cfg = fedgen.CONFIGS[4]
     t0 = time.time()
     cal = fedgen.make_calibration(cfg)
@@ -363,7 +367,8 @@ def stress_line(sc, torch, stream, workers, tuning, cap_cl, cap_adc, steps):
     gen_s = time.time() - t0
     sizes = np.concatenate([np.diff(e.fed_offset.astype(np.int64)) for e in evs])
     ctx = sc.Context(cal.noise, cal.gain, cal.bad, device=0, stream=stream)
-    ctx.tuning = {k: tuning[k] for k in ("chunk_digis", "tile_waves", "tiles_per_cu", "fed_major")}
+    ctx.tuning = {k: tuning[k] for k in ("chunk_digis", "tile_waves", "tiles_per_cu", "fed_major",
+                                         "stage_bytes")}
     ctx.tuning = {"use_graph": 0}
     d = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs]
     o = [ctx.output(cap_cl, cap_adc) for _ in d]
@@ -374,38 +379,55 @@ def stress_line(sc, torch, stream, workers, tuning, cap_cl, cap_adc, steps):
         torch.cuda.synchronize()
     n_over = sum(1 for s in sts if s == sc.SC_ERR_OVERFLOW)
     need = [(y.n_cl, y.n_adc) for y in o]
-    # retry with the needed sizes
-    o = [ctx.output(max(c, 1), max(a, 1)) for c, a in need]
-    batch = ctx.batch(d, o)
-    r = time_steps(ctx, batch, steps, 2, stream, torch, graph=False)
-    rc2 = ctx.process_batch(batch)[0]
-    torch.cuda.synchronize()
-    # every 16th event again, in a batch of its own with capacities that always suffice (an
-    # event's results do not depend on the rest of its batch)
+    # every 16th event in a batch of its own with capacities that always suffice (an event's
+    # results do not depend on the rest of its batch)
     sample = list(range(0, len(d), 16))
     safe = [ctx.output(*sc.safe_caps(d[i])) for i in sample]
     ctx.process_events([d[i] for i in sample], safe)
-    ok = all(np.array_equal(o[i].to_numpy()[0], b.to_numpy()[0]) and
-             np.array_equal(o[i].to_numpy()[1], b.to_numpy()[1]) for i, b in zip(sample, safe))
+    ref = [(b.to_numpy()[0], b.to_numpy()[1]) for b in safe]
     del safe
-    b = algorithmic_bytes(evs, [(y.n_cl, y.n_adc) for y in o], cfg.n_fed)
-    k = r["kernel_ms"]
+    b = algorithmic_bytes(evs, need, cfg.n_fed)
+
+    def retry():
+        """The batch with the needed capacities, timed, and checked against the safe launch."""
+        out = [ctx.output(max(c, 1), max(a, 1)) for c, a in need]
+        batch = ctx.batch(d, out)
+        r = time_steps(ctx, batch, steps, 2, stream, torch, graph=False)
+        rc2 = ctx.process_batch(batch)[0]
+        torch.cuda.synchronize()
+        ok = all(np.array_equal(out[i].to_numpy()[0], c) and np.array_equal(out[i].to_numpy()[1], a)
+                 for i, (c, a) in zip(sample, ref))
+        k = r["kernel_ms"]
+        stage = ctx.tuning["stage_bytes"]
+        return {"tuning": {t: ctx.tuning[t] for t in ("chunk_digis", "tile_waves", "tiles_per_cu",
+                                                      "fed_major", "stage_bytes")},
+                "feds_larger_than_lds_stage": float(np.mean(sizes > stage - STAGE_SLACK)),
+                "status": rc2, "events_per_s": len(evs) * steps / r["elapsed_s"],
+                "ms_per_step": r["elapsed_s"] / steps * 1e3, "kernel_ms": k,
+                "hbm_frac": (b / (k * 1e-3) / 1e9 / HBM_PEAK_GBS) if k else None,
+                "cross_check": ("bit-identical to safe-capacity launches (every 16th event)"
+                                if ok else "MISMATCH")}
+
+    headline = retry()
+    t0 = time.time()
+    best = ctx.autotune(d[:64])
+    tune_s = time.time() - t0
+    ctx.tuning = dict(best, use_graph=0)
+    tuned = retry()
+    tuned["tuned_by"] = f"autotuner on 64 of the stress events ({tune_s:.1f} s)"
     ctx.close()
     return {
         "workload": f"stress: {len(evs)} events x {cfg.n_fed} FEDs at 6% occupancy, width "
                     "1+Geometric(0.25) capped at 32, 1% bad strips, noise U[2,10]",
         "generation_s": gen_s,
         "zs_mb": sum(e.zs.size for e in evs) / 1e6,
-        "feds_larger_than_lds_stage": float(np.mean(sizes > STAGE_BYTES)),
+        "fed_bytes_mean": float(sizes.mean()), "fed_bytes_max": int(sizes.max()),
+        "clusters": int(sum(c for c, _ in need)),
+        "algorithmic_bytes_per_launch": b,
         "first_launch": {"capacities": [cap_cl, cap_adc], "status": rc,
                          "events_overflowed": n_over, "kernel_ms": first_ms},
-        "retry": {"status": rc2, "events_per_s": len(evs) * steps / r["elapsed_s"],
-                  "ms_per_step": r["elapsed_s"] / steps * 1e3, "kernel_ms": k,
-                  "clusters": int(sum(c for c, _ in need)),
-                  "algorithmic_bytes_per_launch": b,
-                  "hbm_frac": (b / (k * 1e-3) / 1e9 / HBM_PEAK_GBS) if k else None},
-        "cross_check": ("retry bit-identical to a safe-capacity launch (every 16th event)" if ok
-                        else "MISMATCH"),
+        "retry": headline,
+        "retry_autotuned": tuned,
     }
 
 

@@ -162,6 +162,11 @@ typedef struct {
                                 until the look-back's wait bound reports SC_ERR_DEVICE. Other
                                 values are taken as 1. */
     uint32_t use_graph;      /* 1: replay the batched launch as a captured hipGraph */
+    uint32_t stage_bytes;    /* LDS bytes that stage a tile's FED: 0 or 6656 (FEDs of up to 6640
+                                bytes), or 10240 (up to 10224 bytes, with fewer resident tiles)
+                                for tile_waves 2 with chunk_digis 2048 or 2880, and tile_waves 4
+                                with 4096. A larger FED is read from global memory instead: the
+                                same results, more slowly. */
 } sc_tuning;
 
 /* Counters of a context. */

@@ -79,7 +79,7 @@ class ScGeometry(ctypes.Structure):
 class ScTuning(ctypes.Structure):
     _fields_ = [("chunk_digis", ctypes.c_uint32), ("tile_waves", ctypes.c_uint32),
                 ("tiles_per_cu", ctypes.c_uint32), ("fed_major", ctypes.c_uint32),
-                ("use_graph", ctypes.c_uint32)]
+                ("use_graph", ctypes.c_uint32), ("stage_bytes", ctypes.c_uint32)]
 
 
 class ScStats(ctypes.Structure):

@@ -74,8 +74,9 @@ hipError_t launch_derive_calib(const float* noise, const float* gain, const uint
                                uint32_t n_fed, float* noise_out, hipStream_t stream);
 // Clears n_state look-back words (n_ev x n_fed), the queue and the results.
 hipError_t launch_reset(const FusedArgs& a, uint32_t n_state, hipStream_t stream);
+// stage: the LDS stage size in bytes of the tuning (0: the small one)
 hipError_t launch_fused(const FusedArgs& a, uint32_t tile_waves, uint32_t chunk_digis,
-                        uint32_t grid, hipStream_t stream);
+                        uint32_t stage, uint32_t grid, hipStream_t stream);
 hipError_t launch_cluster_dense(const uint8_t* adc_dense, const FusedArgs& a,
                                 uint32_t tile_waves, uint32_t chunk_digis, uint32_t grid,
                                 hipStream_t stream);
@@ -94,9 +95,13 @@ struct HitDesc {
 hipError_t launch_hits(const HitDesc* d, uint32_t n_ev, uint32_t max_n, const uint32_t* chan,
                        const float* mod, uint32_t n_channels, hipStream_t stream);
 
-// Resident workgroups per compute unit for a tile shape (waves per tile, digis per chunk).
-int fused_blocks_per_cu(uint32_t tile_waves, uint32_t chunk_digis, bool dense, bool modules);
-bool tile_shape_supported(uint32_t tile_waves, uint32_t chunk_digis);
+// Resident workgroups per compute unit for a tile shape (waves per tile, digis per chunk, LDS
+// stage bytes; 0 is the small stage).
+int fused_blocks_per_cu(uint32_t tile_waves, uint32_t chunk_digis, bool dense, bool modules,
+                        uint32_t stage);
+bool tile_shape_supported(uint32_t tile_waves, uint32_t chunk_digis, uint32_t stage);
+// The stage size a tuning's stage value stands for (0: the small one).
+uint32_t stage_bytes_of(uint32_t stage);
 // Whether a shape's wave lists hold a module row (768 digis): needed while modules are set.
 bool tile_shape_supports_modules(uint32_t tile_waves, uint32_t chunk_digis);
 

@@ -228,9 +228,13 @@ __device__ __forceinline__ uint32_t lds_u16(const uint8_t* buf, uint32_t o) {
     return __builtin_amdgcn_alignbyte(w[1], w[0], o & 3u) & 0xffffu;
 }
 
-template <int W, int DW>
+// LDS stage sizes: the small one holds a FED of full-detector events at 5 % occupancy, the
+// large one (fewer resident tiles) a FED of the 6 %, long-cluster stress events.
+constexpr int kStageSmall = 6656, kStageLarge = 10240;
+
+template <int W, int DW, int S = kStageSmall>
 struct TileSmem {
-    static constexpr int kStageBytes = 6656;   // a FED of full-detector events at 5 % occupancy
+    static constexpr int kStageBytes = S;
     static constexpr int kStageData = kStageBytes - 16;   // FED bytes that fit (alignment slack)
     alignas(16) uint8_t stage[kStageBytes + 16];         // the FED's bytes (+ readable pad)
     uint32_t digi[W * DW];                               // wave w: [w*DW, (w+1)*DW)
@@ -246,6 +250,7 @@ struct TileSmem {
 
 // Two-wave tiles of 2880 digis fit eight to a CU (160 KiB of LDS).
 static_assert(sizeof(TileSmem<2, 1440>) <= 160 * 1024 / 8, "eight two-wave tiles per CU");
+static_assert(sizeof(TileSmem<2, 1440, kStageLarge>) <= 160 * 1024 / 6, "six with the large stage");
 
 // Workgroup barrier (every wave of the tile passes it); a no-op for single-wave tiles.
 __device__ __forceinline__ void tile_sync() { __syncthreads(); }
@@ -264,8 +269,8 @@ __device__ __forceinline__ u32x4 load_gain_vec(const float* gains) {
     const uint32_t i = lane() < kGainVecs ? lane() : kGainVecs - 1u;
     return gc(reinterpret_cast<const u32x4*>(gains))[i];
 }
-template <int W, int DW>
-__device__ __forceinline__ void store_gain_vec(TileSmem<W, DW>& sm, u32x4 v) {
+template <int W, int DW, int S>
+__device__ __forceinline__ void store_gain_vec(TileSmem<W, DW, S>& sm, u32x4 v) {
     const uint32_t i = lane() < kGainVecs ? lane() : kGainVecs - 1u;
     reinterpret_cast<u32x4*>(sm.gain)[i] = v;
 }
@@ -276,11 +281,11 @@ __device__ __forceinline__ void store_gain_vec(TileSmem<W, DW>& sm, u32x4 v) {
 // aligned 16-byte pieces, all issued before the first is stored; each piece holds at least one
 // byte of [gsrc, gsrc+n), so it lies inside the 4 KiB page of a byte of the buffer. With gains
 // != nullptr the FED's APV gains are loaded in the same batch (by wave 0).
-template <int NT, int W, int DW>
-__device__ __forceinline__ uint32_t stage_bytes(TileSmem<W, DW>& sm, uint32_t t,
+template <int NT, int W, int DW, int S>
+__device__ __forceinline__ uint32_t stage_bytes(TileSmem<W, DW, S>& sm, uint32_t t,
                                                 const uint8_t* gsrc, uint32_t n,
                                                 const float* gains) {
-    constexpr int K = (TileSmem<W, DW>::kStageBytes + 16 * NT - 1) / (16 * NT);
+    constexpr int K = (TileSmem<W, DW, S>::kStageBytes + 16 * NT - 1) / (16 * NT);
     const uintptr_t a = reinterpret_cast<uintptr_t>(gsrc);
     const uintptr_t a0 = a & ~uintptr_t(15);
     const uint32_t delta = (uint32_t)(a - a0);
@@ -320,10 +325,10 @@ struct WalkResult {
 
 // Stages the FED (and its gains) and walks its length fields; the channel positions and lengths
 // go to LDS. Every wave of the tile calls it (it contains the tile's barriers).
-template <int W, int DW>
-__device__ WalkResult stage_and_walk(TileSmem<W, DW>& sm, const uint8_t* g, uint32_t L,
+template <int W, int DW, int S>
+__device__ WalkResult stage_and_walk(TileSmem<W, DW, S>& sm, const uint8_t* g, uint32_t L,
                                      const float* gains) {
-    constexpr uint32_t cap = TileSmem<W, DW>::kStageData;
+    constexpr uint32_t cap = TileSmem<W, DW, S>::kStageData;
     const bool fits = L <= cap;
     if (fits) {
         const uint32_t delta = stage_bytes<kWave * W>(sm, threadIdx.x, g, L, gains);
@@ -338,7 +343,7 @@ __device__ WalkResult stage_and_walk(TileSmem<W, DW>& sm, const uint8_t* g, uint
             // a record fits the FED when its end is <= L, and since ends only grow, the records
             // that fit come first (past the first one that does not, the reads stay inside the
             // stage and are unused). Ends stay below 2^23 (96 x (2 + 65535)): no sum wraps.
-            constexpr uint32_t omax = TileSmem<W, DW>::kStageBytes - 2;
+            constexpr uint32_t omax = TileSmem<W, DW, S>::kStageBytes - 2;
             uint32_t pos = 0;
             uint32_t vpos0 = 0, vpos1 = 0;
             auto step = [&](uint32_t k, uint32_t& vpos) {
@@ -413,8 +418,8 @@ __device__ WalkResult stage_and_walk(TileSmem<W, DW>& sm, const uint8_t* g, uint
 
 // ---- record validation, one lane per channel ----------------------------------------------
 // Returns the channel's digi count (0 if malformed) and writes its status into ch_st.
-template <class P, int W, int DW>
-__device__ __forceinline__ uint32_t check_channel(TileSmem<W, DW>& sm, P src, uint32_t ch,
+template <class P, int W, int DW, int S>
+__device__ __forceinline__ uint32_t check_channel(TileSmem<W, DW, S>& sm, P src, uint32_t ch,
                                                   const WalkResult& w) {
     uint32_t st = w.trailing ? (uint32_t)SC_CH_FED_TRAILING : 0u;
     uint32_t nd = 0;
@@ -445,8 +450,8 @@ __device__ __forceinline__ uint32_t check_channel(TileSmem<W, DW>& sm, P src, ui
 
 // The channel group [c_lo, c_hi) of wave w: digi counts -> offsets in the group (ch_base) and
 // its split into chunks of at most DW digis; returns the number of chunks. Wave-local.
-template <bool kMod, int W, int DW, class CountFn>
-__device__ uint32_t plan_chunks(TileSmem<W, DW>& sm, uint32_t w, uint32_t c_lo, uint32_t c_hi,
+template <bool kMod, int W, int DW, int S, class CountFn>
+__device__ uint32_t plan_chunks(TileSmem<W, DW, S>& sm, uint32_t w, uint32_t c_lo, uint32_t c_hi,
                                 Joins J, CountFn count, uint32_t& total) {
     uint32_t carry = 0;
     for (uint32_t base = c_lo; base < c_hi; base += kWave) {
@@ -504,12 +509,12 @@ __device__ uint32_t plan_chunks(TileSmem<W, DW>& sm, uint32_t w, uint32_t c_lo, 
 // list's other slots never carry bit 31: the digi words use bits 0-27, and the kernel clears
 // the list before its first tile. From global memory (a FED larger than the stage): one lane
 // per channel expands its runs, four ADC bytes per iteration.
-template <bool kStaged, class P, int W, int DW>
-__device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, uint32_t* dl, P src,
+template <bool kStaged, class P, int W, int DW, int S>
+__device__ __forceinline__ void build_zs(TileSmem<W, DW, S>& sm, uint32_t w, uint32_t* dl, P src,
                                          uint32_t c0, uint32_t c1) {
     const uint32_t b0 = sm.ch_base[c0 + w];
     if constexpr (kStaged) {
-        static_assert(TileSmem<W, DW>::kStageBytes + 16 <= (1 << 13), "marker source offsets are 13 bits");
+        static_assert(TileSmem<W, DW, S>::kStageBytes + 16 <= (1 << 16), "marker source offsets are 16 bits");
         __builtin_amdgcn_s_setprio(2);   // a serial pass that the digi pass waits for
         for (uint32_t ch = c0 + lane(); ch < c1; ch += kWave) {
             if (sm.ch_st[ch] & SC_CH_MALFORMED) continue;
@@ -538,7 +543,7 @@ __device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, uint32
             const uint32_t hv = __shfl(v, (int)hl);
             const uint32_t m = mine ? hv : carry_m;
             const uint32_t k = j - (mine ? j0 + hl : carry_j);
-            const uint32_t so = (m >> 15) & 0x1fffu, first = m & 0xffu, ch = (m >> 8) & 0x7fu;
+            const uint32_t so = (m >> 15) & 0xffffu, first = m & 0xffu, ch = (m >> 8) & 0x7fu;
             if (j < n) dl[j] = (ch << 16) | ((first + k) << 8) | src[so + k];
             if (heads) {
                 const uint32_t last = 63u - (uint32_t)__clzll((long long)heads);
@@ -576,8 +581,8 @@ __device__ __forceinline__ void build_zs(TileSmem<W, DW>& sm, uint32_t w, uint32
 }
 
 // Dense rows of channels [c0, c1) -> digi list; 4 channels per wave step, 16 lanes x 16 strips.
-template <int W, int DW>
-__device__ __forceinline__ void build_dense(TileSmem<W, DW>& sm, uint32_t w, uint32_t* dl,
+template <int W, int DW, int S>
+__device__ __forceinline__ void build_dense(TileSmem<W, DW, S>& sm, uint32_t w, uint32_t* dl,
                                             const uint8_t* rows, uint32_t c0, uint32_t c1) {
     const uint32_t b0 = sm.ch_base[c0 + w];
     for (uint32_t cb = c0; cb < c1; cb += 4) {
@@ -941,8 +946,8 @@ __device__ __forceinline__ uint32_t corrected_adc(uint32_t d, float g) {
 // Records and member ADCs of the digi list dl[0, nd) at their final positions, 128 digis per
 // step, two per lane (A = base + 2l, B = A + 1) as in forming. The member ADCs are
 // gain-corrected here.
-template <bool kMod, int W, int DW>
-__device__ __forceinline__ void write_pass(const TileSmem<W, DW>& sm, const uint32_t* dl,
+template <bool kMod, int W, int DW, int S>
+__device__ __forceinline__ void write_pass(const TileSmem<W, DW, S>& sm, const uint32_t* dl,
                                            uint32_t nd, uint32_t fed, const EventDesc& ev,
                                            uint32_t base_cl, uint32_t base_adc) {
     constexpr uint32_t kStep = 2 * kWave;
@@ -1109,8 +1114,8 @@ __device__ __forceinline__ void publish_and_lookback(unsigned long long* row, ui
 }
 
 // Status bits of channels [c_lo, c_hi) -> optional per-channel output and the event's flags.
-template <int W, int DW>
-__device__ __forceinline__ void emit_status(TileSmem<W, DW>& sm, uint32_t c_lo, uint32_t c_hi,
+template <int W, int DW, int S>
+__device__ __forceinline__ void emit_status(TileSmem<W, DW, S>& sm, uint32_t c_lo, uint32_t c_hi,
                                             uint8_t* chan_status, uint32_t f,
                                             uint32_t* flags_out) {
     uint32_t any = 0;
@@ -1130,8 +1135,8 @@ __device__ __forceinline__ void emit_status(TileSmem<W, DW>& sm, uint32_t c_lo, 
 // form their groups, exchange their counts in LDS, and wave 0 publishes the FED's counts and
 // looks back over the earlier FEDs of the event; each group's output offset is then the FED's
 // plus the counts of the groups before it. Every wave passes the same two barriers.
-template <int W, int DW, bool kMod, class BuildFn>
-__device__ void cluster_group(const FusedArgs& A, TileSmem<W, DW>& sm, const EventDesc& ev,
+template <int W, int DW, bool kMod, int S, class BuildFn>
+__device__ void cluster_group(const FusedArgs& A, TileSmem<W, DW, S>& sm, const EventDesc& ev,
                               uint32_t e, uint32_t f, uint32_t w, uint32_t n_chunks,
                               Joins J, BuildFn build) {
     const uint32_t n_fed = A.cal.n_fed;
@@ -1222,8 +1227,8 @@ __device__ __forceinline__ Joins fed_joins(const DeviceCalib& cal, uint32_t f) {
     }
 }
 
-template <int W, int DW, bool kMod>
-__device__ void zs_tile(const FusedArgs& A, TileSmem<W, DW>& sm, uint32_t e, uint32_t f) {
+template <int W, int DW, bool kMod, int S>
+__device__ void zs_tile(const FusedArgs& A, TileSmem<W, DW, S>& sm, uint32_t e, uint32_t f) {
     const EventDesc* evp = A.ev + e;
     EventDesc ev;
     ev.zs = uniptr(evp->zs);
@@ -1267,8 +1272,8 @@ __device__ void zs_tile(const FusedArgs& A, TileSmem<W, DW>& sm, uint32_t e, uin
 }
 
 // ---- one FED tile from dense ADC rows (single event) --------------------------------------
-template <int W, int DW, bool kMod>
-__device__ void dense_tile(const FusedArgs& A, TileSmem<W, DW>& sm, const uint8_t* dense,
+template <int W, int DW, bool kMod, int S>
+__device__ void dense_tile(const FusedArgs& A, TileSmem<W, DW, S>& sm, const uint8_t* dense,
                            uint32_t f) {
     const EventDesc* evp = A.ev;
     EventDesc ev;
@@ -1303,8 +1308,8 @@ __device__ void dense_tile(const FusedArgs& A, TileSmem<W, DW>& sm, const uint8_
 // lowest unfinished tile of an event has always been taken and every look-back ends, whatever
 // part of the grid is resident. With several waves per tile, wave 0 takes the ticket and the
 // others read it after a barrier.
-template <int W, int DW>
-__device__ __forceinline__ uint32_t next_tile(TileSmem<W, DW>& sm, uint32_t* queue) {
+template <int W, int DW, int S>
+__device__ __forceinline__ uint32_t next_tile(TileSmem<W, DW, S>& sm, uint32_t* queue) {
     if constexpr (W == 1) {
         return uni(atomicAdd(queue, lane() == 0u ? 1u : 0u));
     } else {
@@ -1373,8 +1378,8 @@ __device__ __forceinline__ uint32_t claim_xcd(uint32_t* queue, uint32_t n_ev, ui
     return n_ev * n_fed;
 }
 
-template <int W, int DW>
-__device__ __forceinline__ uint32_t next_tile_xcd(TileSmem<W, DW>& sm, uint32_t* queue,
+template <int W, int DW, int S>
+__device__ __forceinline__ uint32_t next_tile_xcd(TileSmem<W, DW, S>& sm, uint32_t* queue,
                                                   uint32_t n_ev, uint32_t n_fed, uint32_t groups,
                                                   XcdCursor& cur) {
     if constexpr (W == 1) {
@@ -1392,8 +1397,8 @@ __device__ __forceinline__ uint32_t next_tile_xcd(TileSmem<W, DW>& sm, uint32_t*
 
 // Runs tile(e, f) for every tile of an n_ev x n_fed launch, in tile order `order` (0 event-major,
 // 1 FED-major, 2 FED-major per XCD).
-template <int W, int DW, class TileFn>
-__device__ __forceinline__ void run_tiles(TileSmem<W, DW>& sm, uint32_t* queue, uint32_t n_ev,
+template <int W, int DW, int S, class TileFn>
+__device__ __forceinline__ void run_tiles(TileSmem<W, DW, S>& sm, uint32_t* queue, uint32_t n_ev,
                                           uint32_t n_fed, uint32_t order, TileFn tile) {
     const uint32_t n_tiles = n_ev * n_fed;
     const uint32_t groups = gridDim.x < kXcds ? gridDim.x : kXcds;
@@ -1410,18 +1415,18 @@ __device__ __forceinline__ void run_tiles(TileSmem<W, DW>& sm, uint32_t* queue, 
     }
 }
 
-template <int W, int DW, bool kMod>
+template <int W, int DW, bool kMod, int S>
 __global__ __launch_bounds__(kWave * W) void fused_kernel(FusedArgs A) {
-    __shared__ TileSmem<W, DW> sm;
+    __shared__ TileSmem<W, DW, S> sm;
     // the ZS build finds its record markers by bit 31 of the digi list's slots: clear them once
     for (uint32_t i = threadIdx.x; i < (uint32_t)(W * DW); i += kWave * W) sm.digi[i] = 0u;
     run_tiles(sm, A.queue, A.n_ev, A.cal.n_fed, A.fed_major,
               [&](uint32_t e, uint32_t f) { zs_tile<W, DW, kMod>(A, sm, e, f); });
 }
 
-template <int W, int DW, bool kMod>
+template <int W, int DW, bool kMod, int S>
 __global__ __launch_bounds__(kWave * W) void cluster_dense_kernel(const uint8_t* dense, FusedArgs A) {
-    __shared__ TileSmem<W, DW> sm;
+    __shared__ TileSmem<W, DW, S> sm;
     run_tiles(sm, A.queue, 1u, A.cal.n_fed, 1u,
               [&](uint32_t, uint32_t f) { dense_tile<W, DW, kMod>(A, sm, dense, f); });
 }
@@ -1510,13 +1515,13 @@ __global__ void derive_calib_kernel(const float* noise, const float* gain, const
 }
 
 // Resident tiles per CU of a kernel (its LDS and registers), queried once per shape.
-template <int W, int DW, bool kMod>
+template <int W, int DW, bool kMod, int S>
 int blocks_per_cu_for(bool dense) {
     static std::atomic<int> known[2] = {0, 0};
     int nb = known[dense].load(std::memory_order_relaxed);
     if (nb > 0) return nb;
-    hipError_t e = dense ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cluster_dense_kernel<W, DW, kMod>, kWave * W, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_kernel<W, DW, kMod>, kWave * W, 0);
+    hipError_t e = dense ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, cluster_dense_kernel<W, DW, kMod, S>, kWave * W, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_kernel<W, DW, kMod, S>, kWave * W, 0);
     if (e != hipSuccess || nb < 1) return 1;
     known[dense].store(nb, std::memory_order_relaxed);
     return nb;
@@ -1525,38 +1530,51 @@ int blocks_per_cu_for(bool dense) {
 // Module rows need a whole row (up to 768 digis) in one chunk of a wave's list.
 constexpr int kRowDigis = 3 * kStripsPerChannel;
 
-// Tile shapes: W waves per tile and chunk_digis digis per tile (chunk_digis / W per wave).
+// Tile shapes: W waves per tile, chunk_digis digis per tile (chunk_digis / W per wave) and the
+// stage size; the large stage exists for three shapes. stage 0 means the small one.
 template <class F>
-bool dispatch(uint32_t w, uint32_t d, F&& f) {
-#define SC_CASE(WW, DD) \
-    if (w == WW && d == DD) { f(std::integral_constant<int, WW>{}, std::integral_constant<int, DD / WW>{}); return true; }
-    SC_CASE(1, 1024) SC_CASE(1, 2048) SC_CASE(1, 3072) SC_CASE(1, 4096)
-    SC_CASE(2, 2048) SC_CASE(2, 2880) SC_CASE(2, 3072) SC_CASE(2, 4096)
-    SC_CASE(4, 2048) SC_CASE(4, 3072) SC_CASE(4, 4096)
+bool dispatch(uint32_t w, uint32_t d, uint32_t stage, F&& f) {
+    if (stage == 0u) stage = (uint32_t)kStageSmall;
+#define SC_CASE(WW, DD, SS) \
+    if (w == WW && d == DD && stage == (uint32_t)SS) { \
+        f(std::integral_constant<int, WW>{}, std::integral_constant<int, DD / WW>{}, \
+          std::integral_constant<int, SS>{}); \
+        return true; \
+    }
+    SC_CASE(1, 1024, kStageSmall) SC_CASE(1, 2048, kStageSmall) SC_CASE(1, 3072, kStageSmall)
+    SC_CASE(1, 4096, kStageSmall)
+    SC_CASE(2, 2048, kStageSmall) SC_CASE(2, 2880, kStageSmall) SC_CASE(2, 3072, kStageSmall)
+    SC_CASE(2, 4096, kStageSmall)
+    SC_CASE(4, 2048, kStageSmall) SC_CASE(4, 3072, kStageSmall) SC_CASE(4, 4096, kStageSmall)
+    SC_CASE(2, 2048, kStageLarge) SC_CASE(2, 2880, kStageLarge) SC_CASE(4, 4096, kStageLarge)
 #undef SC_CASE
     return false;
 }
 
 }  // namespace
 
-bool tile_shape_supported(uint32_t waves, uint32_t d) {
-    return dispatch(waves, d, [](auto, auto) {});
+bool tile_shape_supported(uint32_t waves, uint32_t d, uint32_t stage) {
+    return dispatch(waves, d, stage, [](auto, auto, auto) {});
 }
 
 bool tile_shape_supports_modules(uint32_t waves, uint32_t d) {
     bool ok = false;
-    dispatch(waves, d, [&](auto, auto DW) { ok = decltype(DW)::value >= kRowDigis; });
+    dispatch(waves, d, 0u, [&](auto, auto DW, auto) { ok = decltype(DW)::value >= kRowDigis; });
     return ok;
 }
 
-int fused_blocks_per_cu(uint32_t waves, uint32_t d, bool dense, bool modules) {
+uint32_t stage_bytes_of(uint32_t stage) { return stage ? stage : (uint32_t)kStageSmall; }
+
+int fused_blocks_per_cu(uint32_t waves, uint32_t d, bool dense, bool modules, uint32_t stage) {
     int nb = 1;
-    dispatch(waves, d, [&](auto W, auto DW) {
-        constexpr int w = decltype(W)::value, dw = decltype(DW)::value;
+    // (the dense front end never reads the stage: it runs with the small one)
+    dispatch(waves, d, dense ? 0u : stage, [&](auto W, auto DW, auto SS) {
+        constexpr int w = decltype(W)::value, dw = decltype(DW)::value, st = decltype(SS)::value;
         if constexpr (dw >= kRowDigis) {
-            nb = modules ? blocks_per_cu_for<w, dw, true>(dense) : blocks_per_cu_for<w, dw, false>(dense);
+            nb = modules ? blocks_per_cu_for<w, dw, true, st>(dense)
+                         : blocks_per_cu_for<w, dw, false, st>(dense);
         } else {
-            nb = blocks_per_cu_for<w, dw, false>(dense);
+            nb = blocks_per_cu_for<w, dw, false, st>(dense);
         }
     });
     return nb;
@@ -1583,19 +1601,19 @@ hipError_t launch_reset(const FusedArgs& a, uint32_t n_state, hipStream_t stream
 }
 
 // The module-row kernels (cal.joins set) exist for the shapes whose wave lists hold a row.
-hipError_t launch_fused(const FusedArgs& a, uint32_t waves, uint32_t d, uint32_t grid,
-                        hipStream_t stream) {
+hipError_t launch_fused(const FusedArgs& a, uint32_t waves, uint32_t d, uint32_t stage,
+                        uint32_t grid, hipStream_t stream) {
     (void)hipGetLastError();
     const bool mod = a.cal.joins != nullptr;
     bool ok = false;
-    dispatch(waves, d, [&](auto W, auto DW) {
-        constexpr int w = decltype(W)::value, dw = decltype(DW)::value;
+    dispatch(waves, d, stage, [&](auto W, auto DW, auto SS) {
+        constexpr int w = decltype(W)::value, dw = decltype(DW)::value, st = decltype(SS)::value;
         if constexpr (dw >= kRowDigis) {
-            if (mod) hipLaunchKernelGGL((fused_kernel<w, dw, true>), dim3(grid), dim3(kWave * w), 0, stream, a);
-            else     hipLaunchKernelGGL((fused_kernel<w, dw, false>), dim3(grid), dim3(kWave * w), 0, stream, a);
+            if (mod) hipLaunchKernelGGL((fused_kernel<w, dw, true, st>), dim3(grid), dim3(kWave * w), 0, stream, a);
+            else     hipLaunchKernelGGL((fused_kernel<w, dw, false, st>), dim3(grid), dim3(kWave * w), 0, stream, a);
             ok = true;
         } else if (!mod) {
-            hipLaunchKernelGGL((fused_kernel<w, dw, false>), dim3(grid), dim3(kWave * w), 0, stream, a);
+            hipLaunchKernelGGL((fused_kernel<w, dw, false, st>), dim3(grid), dim3(kWave * w), 0, stream, a);
             ok = true;
         }
     });
@@ -1607,14 +1625,14 @@ hipError_t launch_cluster_dense(const uint8_t* dense, const FusedArgs& a, uint32
     (void)hipGetLastError();
     const bool mod = a.cal.joins != nullptr;
     bool ok = false;
-    dispatch(waves, d, [&](auto W, auto DW) {
-        constexpr int w = decltype(W)::value, dw = decltype(DW)::value;
+    dispatch(waves, d, 0u, [&](auto W, auto DW, auto SS) {
+        constexpr int w = decltype(W)::value, dw = decltype(DW)::value, st = decltype(SS)::value;
         if constexpr (dw >= kRowDigis) {
-            if (mod) hipLaunchKernelGGL((cluster_dense_kernel<w, dw, true>), dim3(grid), dim3(kWave * w), 0, stream, dense, a);
-            else     hipLaunchKernelGGL((cluster_dense_kernel<w, dw, false>), dim3(grid), dim3(kWave * w), 0, stream, dense, a);
+            if (mod) hipLaunchKernelGGL((cluster_dense_kernel<w, dw, true, st>), dim3(grid), dim3(kWave * w), 0, stream, dense, a);
+            else     hipLaunchKernelGGL((cluster_dense_kernel<w, dw, false, st>), dim3(grid), dim3(kWave * w), 0, stream, dense, a);
             ok = true;
         } else if (!mod) {
-            hipLaunchKernelGGL((cluster_dense_kernel<w, dw, false>), dim3(grid), dim3(kWave * w), 0, stream, dense, a);
+            hipLaunchKernelGGL((cluster_dense_kernel<w, dw, false, st>), dim3(grid), dim3(kWave * w), 0, stream, dense, a);
             ok = true;
         }
     });

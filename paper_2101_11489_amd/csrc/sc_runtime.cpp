@@ -130,11 +130,11 @@ struct Workspace {
 size_t devbuf_size(size_t bytes) { return bytes ? align_up(std::max<size_t>(bytes, 256), 4096) : 0; }
 
 struct GraphKey {
-    uint32_t n_ev, chunk, waves, grid, fed_major, modules;
+    uint32_t n_ev, chunk, waves, grid, fed_major, modules, stage;
     uint64_t gen;
     bool operator<(const GraphKey& o) const {
-        return std::tie(n_ev, chunk, waves, grid, fed_major, modules, gen) <
-               std::tie(o.n_ev, o.chunk, o.waves, o.grid, o.fed_major, o.modules, o.gen);
+        return std::tie(n_ev, chunk, waves, grid, fed_major, modules, stage, gen) <
+               std::tie(o.n_ev, o.chunk, o.waves, o.grid, o.fed_major, o.modules, o.stage, o.gen);
     }
 };
 
@@ -229,7 +229,7 @@ sc_status device_fail(sc_ctx* c, hipError_t e, const char* where) {
 
 uint32_t grid_for(const sc_ctx* c, uint32_t n_tiles, bool dense) {
     const int occ = std::max(1, fused_blocks_per_cu(c->tuning.tile_waves, c->tuning.chunk_digis,
-                                                    dense, c->modules));
+                                                    dense, c->modules, c->tuning.stage_bytes));
     const uint32_t per_cu = std::max<uint32_t>(1, std::min<uint32_t>(c->tuning.tiles_per_cu, occ));
     const uint32_t g = per_cu * (uint32_t)std::max(1, c->n_cu);
     return std::max<uint32_t>(1, std::min<uint32_t>(g, n_tiles));
@@ -483,7 +483,9 @@ hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bo
     }
     if (timed && (e = hipEventRecord(c->ev0, s))) return e;
     const uint32_t grid = grid_for(c, n * c->n_fed, false);
-    if ((e = launch_fused(a, c->tuning.tile_waves, c->tuning.chunk_digis, grid, s))) return e;
+    if ((e = launch_fused(a, c->tuning.tile_waves, c->tuning.chunk_digis, c->tuning.stage_bytes,
+                          grid, s)))
+        return e;
     ws.clean = false;
     if (timed && (e = hipEventRecord(c->ev1, s))) return e;
     return hipMemcpyAsync(ws.h_res.p, ws.res.p, sizeof(EventResult) * n, hipMemcpyDeviceToHost, s);
@@ -493,7 +495,7 @@ hipError_t enqueue_batch(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s, bo
 hipError_t enqueue_batch_graph(sc_ctx* c, Workspace& ws, uint32_t n, hipStream_t s) {
     const uint32_t grid = grid_for(c, n * c->n_fed, false);
     GraphKey k{n, c->tuning.chunk_digis, c->tuning.tile_waves, grid, c->tuning.fed_major,
-               c->modules ? 1u : 0u, ws.generation};
+               c->modules ? 1u : 0u, stage_bytes_of(c->tuning.stage_bytes), ws.generation};
     auto it = c->graphs.find(k);
     hipError_t e;
     if (it == c->graphs.end()) {
@@ -595,10 +597,11 @@ bool load_tuning(sc_ctx* c) {
     if (p == std::string::npos) return false;
     p = txt.find('[', p);
     if (p == std::string::npos) return false;
-    unsigned a = 0, w = 0, b = 0, d = 0, g = 0;
-    if (std::sscanf(txt.c_str() + p, "[%u,%u,%u,%u,%u]", &a, &w, &b, &d, &g) != 5) return false;
-    if (!tile_shape_supported(w, a) || b < 1 || b > 32) return false;
-    c->tuning = sc_tuning{a, w, b, d > 2u ? 1u : d, g ? 1u : 0u};
+    unsigned a = 0, w = 0, b = 0, d = 0, g = 0, st = 0;
+    const int got = std::sscanf(txt.c_str() + p, "[%u,%u,%u,%u,%u,%u]", &a, &w, &b, &d, &g, &st);
+    if (got < 5) return false;   // entries written before the stage size was tuned have 5
+    if (!tile_shape_supported(w, a, st) || b < 1 || b > 32) return false;
+    c->tuning = sc_tuning{a, w, b, d > 2u ? 1u : d, g ? 1u : 0u, stage_bytes_of(st)};
     return true;
 }
 
@@ -618,9 +621,9 @@ void save_tuning(const sc_ctx* c) {
         }
     }
     char buf[96];
-    std::snprintf(buf, sizeof buf, "[%u,%u,%u,%u,%u]", c->tuning.chunk_digis,
+    std::snprintf(buf, sizeof buf, "[%u,%u,%u,%u,%u,%u]", c->tuning.chunk_digis,
                   c->tuning.tile_waves, c->tuning.tiles_per_cu, c->tuning.fed_major,
-                  c->tuning.use_graph);
+                  c->tuning.use_graph, stage_bytes_of(c->tuning.stage_bytes));
     entries[tune_key(c)] = buf;
     std::ofstream f(c->tune_cache, std::ios::trunc);
     f << "{\n";
@@ -1006,7 +1009,7 @@ sc_status sc_create(const sc_calib* cal, const sc_options* opt_in, sc_ctx** out)
         return fail(nullptr, SC_ERR_DEVICE, "hipGetDeviceProperties");
     c->n_cu = prop.multiProcessorCount;
     c->device_name = prop.gcnArchName;
-    c->tuning = sc_tuning{2880, 2, 32, 2, 1};
+    c->tuning = sc_tuning{2880, 2, 32, 2, 1, stage_bytes_of(0)};
     load_tuning(c.get());
     if (opt.stream) {
         c->stream = static_cast<hipStream_t>(opt.stream);
@@ -1464,7 +1467,7 @@ sc_status sc_process_events_static(sc_ctx* c, const sc_event* ev, uint32_t n, sc
     // the array keeps the last call's contents: clear the look-back words, queue and results
     SC_HIP(c, launch_reset(a, n * c->n_fed, s));
     SC_HIP(c, hipEventRecord(c->ev0, s));
-    SC_HIP(c, launch_fused(a, c->tuning.tile_waves, c->tuning.chunk_digis,
+    SC_HIP(c, launch_fused(a, c->tuning.tile_waves, c->tuning.chunk_digis, c->tuning.stage_bytes,
                            grid_for(c, n * c->n_fed, false), s));
     SC_HIP(c, hipEventRecord(c->ev1, s));
     SC_HIP(c, hipMemcpyAsync(hr, a.res, sizeof(EventResult) * n, hipMemcpyDeviceToHost, s));
@@ -1599,17 +1602,19 @@ sc_status sc_get_tuning(const sc_ctx* c, sc_tuning* t) {
 
 sc_status sc_set_tuning(sc_ctx* c, const sc_tuning* t) {
     if (!c || !t) return SC_ERR_INVALID_ARG;
-    if (!tile_shape_supported(t->tile_waves, t->chunk_digis) || t->tiles_per_cu < 1 ||
-        t->tiles_per_cu > 32)
+    if (!tile_shape_supported(t->tile_waves, t->chunk_digis, t->stage_bytes) ||
+        t->tiles_per_cu < 1 || t->tiles_per_cu > 32)
         return fail(c, SC_ERR_INVALID_ARG,
                     "unsupported tuning (tile_waves 1, 2 or 4; chunk_digis 2048, 3072 or 4096, "
-                    "1024 with one wave, 2880 with two)");
+                    "1024 with one wave, 2880 with two; stage_bytes 0 or 6656, or 10240 with "
+                    "2 x 2048, 2 x 2880 or 4 x 4096)");
     if (c->modules && !tile_shape_supports_modules(t->tile_waves, t->chunk_digis))
         return fail(c, SC_ERR_INVALID_ARG,
                     "tile shape holds no module row (768 digis per wave) while modules are set");
     c->tuning = *t;
     c->tuning.fed_major = t->fed_major > 2u ? 1u : t->fed_major;
     c->tuning.use_graph = t->use_graph ? 1 : 0;
+    c->tuning.stage_bytes = stage_bytes_of(t->stage_bytes);
     return SC_OK;
 }
 
@@ -1655,11 +1660,13 @@ sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best
     // best of those with fewer resident tiles per compute unit (fewer tiles in flight can shorten
     // the look-back waits of the FEDs that follow).
     std::vector<sc_tuning> cands;
-    for (uint32_t w : {1u, 2u, 4u})
-        for (uint32_t d : {1024u, 2048u, 2880u, 3072u, 4096u})
-            for (uint32_t fm : {0u, 1u, 2u})
-                if (tile_shape_supported(w, d) && (!c->modules || tile_shape_supports_modules(w, d)))
-                    cands.push_back(sc_tuning{d, w, 32, fm, 0});
+    for (uint32_t st : {stage_bytes_of(0), 10240u})
+        for (uint32_t w : {1u, 2u, 4u})
+            for (uint32_t d : {1024u, 2048u, 2880u, 3072u, 4096u})
+                for (uint32_t fm : {0u, 1u, 2u})
+                    if (tile_shape_supported(w, d, st) &&
+                        (!c->modules || tile_shape_supports_modules(w, d)))
+                        cands.push_back(sc_tuning{d, w, 32, fm, 0, st});
     const size_t n_stage1 = cands.size();
     std::vector<uint8_t> ref_cl, ref_adc, cur_cl, cur_adc;
     double best_ms = 1e30;
@@ -1667,7 +1674,7 @@ sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best
     for (size_t ci = 0; ci < cands.size(); ++ci) {
         if (ci == n_stage1) {
             const int occ = fused_blocks_per_cu(best_t.tile_waves, best_t.chunk_digis, false,
-                                                c->modules);
+                                                c->modules, best_t.stage_bytes);
             for (int tpc = occ - 1; tpc >= std::max(1, occ - 3); --tpc) {
                 sc_tuning t = best_t;
                 t.tiles_per_cu = (uint32_t)tpc;

@@ -50,6 +50,24 @@ def test_full_detector_batch_exact(full, waves, chunk):
         ctx.tuning = before
 
 
+LARGE_STAGE = 10240   # sc_tuning.stage_bytes of the large LDS stage (FEDs up to 10224 bytes)
+
+
+@pytest.mark.parametrize("waves,chunk", [(2, 2048), (2, 2880), (4, 4096)])
+def test_full_detector_batch_exact_large_stage(full, waves, chunk):
+    cal, evs, refs, ctx = full
+    before = ctx.tuning
+    ctx.tuning = {"use_graph": 0, "tile_waves": waves, "chunk_digis": chunk,
+                  "stage_bytes": LARGE_STAGE}
+    try:
+        results, rc, sts, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs])
+        assert rc == sc.SC_OK
+        for i, (res, ref) in enumerate(zip(results, refs)):
+            compare_clusters(res[0], res[1], ref, f"large stage, event {i}")
+    finally:
+        ctx.tuning = before
+
+
 @pytest.mark.parametrize("waves,chunk", [(2, 2880), (1, 3072)])
 @pytest.mark.parametrize("graph", [0, 1])
 def test_full_detector_per_xcd_order_exact(full, waves, chunk, graph):
@@ -257,6 +275,26 @@ def test_stress_distribution_and_overflow_batch():
         assert allcl["width"].max() >= 12
 
 
+@pytest.mark.parametrize("waves,chunk", [(2, 2048), (2, 2880), (4, 4096)])
+def test_stress_distribution_large_stage(waves, chunk):
+    """The stress distribution's FEDs (about 8.2 KB) are past the small stage and inside the
+    large one: staged and walked in LDS there, read from global memory with the small stage; the
+    same clusters either way."""
+    cfg = fedgen.CONFIGS[4].with_(n_fed=60)
+    cal = fedgen.make_calibration(cfg)
+    evs = fedgen.make_events(cfg, cal, range(3), workers=3)
+    sizes = np.concatenate([np.diff(e.fed_offset.astype(np.int64)) for e in evs])
+    assert np.mean(sizes > 6640) > 0.9 and np.all(sizes <= LARGE_STAGE - 16)
+    refs = [_oracle(e, cal) for e in evs]
+    with make_ctx(cal.noise, cal.gain, cal.bad) as ctx:
+        ctx.tuning = {"use_graph": 0, "tile_waves": waves, "chunk_digis": chunk,
+                      "stage_bytes": LARGE_STAGE}
+        results, rc, _, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs])
+        assert rc == sc.SC_OK
+        for i, (res, ref) in enumerate(zip(results, refs)):
+            compare_clusters(res[0], res[1], ref, f"stress, large stage, event {i}")
+
+
 def _edge_event(kind):
     n_fed = 3
     noise, gain, bad = calib_arrays(n_fed)
@@ -274,6 +312,11 @@ def _edge_event(kind):
         # 128 isolated strips per channel -> 12288 clusters in one FED
         runs = {c: [(2 * k, [5]) for k in range(128)] for c in range(96)}
         zs, fo = event_from_runs(runs, n_fed)
+    elif kind == "between_stages":
+        # 30 full channels in FED 1: 7.9 KB of ZS (past the small stage, inside the large one)
+        # and 7680 digis (several chunks)
+        runs = {96 + c: [(0, [4] + [3] * 254), (255, [3])] for c in range(30)}
+        zs, fo = event_from_runs(runs, n_fed)
     elif kind == "multichunk_fits_stage":
         # 20 full channels: 5 KB of ZS (fits the stage) but 5120 digis
         runs = {192 + c: [(0, [4] + [3] * 254), (255, [3])] for c in range(20)}
@@ -288,13 +331,15 @@ def _edge_event(kind):
 
 
 @pytest.mark.parametrize("kind", ["all_empty", "zero_length_feds", "full_fed", "alternating_fed",
-                                  "multichunk_fits_stage", "garbage"])
-@pytest.mark.parametrize("shape", [(1024, 1), (3072, 1), (2048, 2), (2880, 2), (4096, 2), (2048, 4)])
+                                  "between_stages", "multichunk_fits_stage", "garbage"])
+@pytest.mark.parametrize("shape", [(1024, 1, 0), (3072, 1, 0), (2048, 2, 0), (2880, 2, 0),
+                                   (4096, 2, 0), (2048, 4, 0), (2880, 2, LARGE_STAGE),
+                                   (4096, 4, LARGE_STAGE)])
 def test_edge_cases(kind, shape):
     zs, fo, noise, gain, bad = _edge_event(kind)
     ref = oracle.process_event(zs, fo, noise, gain, bad)
     with make_ctx(noise, gain, bad) as ctx:
-        ctx.tuning = {"chunk_digis": shape[0], "tile_waves": shape[1]}
+        ctx.tuning = {"chunk_digis": shape[0], "tile_waves": shape[1], "stage_bytes": shape[2]}
         caps = (max(ref.cl.size, 1), max(ref.adc.size, 1))
         (res,), rc, sts, _ = run_fused(ctx, [(zs, fo)], caps=caps, chan_status=True)
         compare_clusters(res[0], res[1], ref, kind)
@@ -429,7 +474,7 @@ def test_autotune_identical_and_cached(full, tmp_path):
             compare_clusters(r[0], r[1], ref, "after autotune")
     with make_ctx(cal.noise, cal.gain, cal.bad, tune_cache=cache) as ctx2:
         t = ctx2.tuning
-        keys = ("chunk_digis", "tile_waves", "tiles_per_cu", "fed_major")
+        keys = ("chunk_digis", "tile_waves", "tiles_per_cu", "fed_major", "stage_bytes")
         assert [t[k] for k in keys] == [best[k] for k in keys]
 
 

@@ -64,6 +64,21 @@ def test_full_detector_module_rows_exact(full, waves, chunk, order):
         ctx.tuning = before
 
 
+@pytest.mark.parametrize("waves,chunk", [(2, 2880), (4, 4096)])
+def test_module_rows_with_the_large_stage(full, waves, chunk):
+    cal, geo, evs, refs, ctx = full
+    before = ctx.tuning
+    ctx.tuning = {"use_graph": 0, "tile_waves": waves, "chunk_digis": chunk, "stage_bytes": 10240}
+    try:
+        results, rc, _, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs[:3]])
+        assert rc == sc.SC_OK
+        for i, (res, ref) in enumerate(zip(results, refs[:3])):
+            compare_clusters(res[0], res[1], ref, f"module rows, large stage, event {i}")
+            assert bary_bit_exact(res[0], ref)
+    finally:
+        ctx.tuning = before
+
+
 def test_graph_replay_and_rows_off_again(full):
     cal, geo, evs, refs, ctx = full
     devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs[:3]]
