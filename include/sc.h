@@ -148,7 +148,8 @@ typedef struct {
 
 /* Performance-relevant choices of the fused kernel (found by sc_autotune). */
 typedef struct {
-    uint32_t chunk_digis;    /* digis a tile holds in LDS per pass: 2048, 3072, 4096; 1024 with 1 wave, 2880 with 2 */
+    uint32_t chunk_digis;    /* digis a tile holds in LDS per pass: 2048, 3072, 4096; 1024 with 1
+                                wave, 2880 with 2, 6144 with 4 and the large stage */
     uint32_t tile_waves;     /* wavefronts per tile: 1, 2 or 4 (each takes 96/W channels) */
     uint32_t tiles_per_cu;   /* cap on resident tiles per compute unit (persistent grid), 1..32 */
     uint32_t fed_major;      /* tile order: 0 event-major; 1 FED-major (a FED's calibration
@@ -165,8 +166,8 @@ typedef struct {
     uint32_t stage_bytes;    /* LDS bytes that stage a tile's FED: 0 or 6656 (FEDs of up to 6640
                                 bytes), or 10240 (up to 10224 bytes, with fewer resident tiles)
                                 for tile_waves 2 with chunk_digis 2048 or 2880, and tile_waves 4
-                                with 4096. A larger FED is read from global memory instead: the
-                                same results, more slowly. */
+                                with 4096 or 6144 (6144 only with this stage). A larger FED is
+                                read from global memory instead: the same results, more slowly. */
 } sc_tuning;
 
 /* Counters of a context. */

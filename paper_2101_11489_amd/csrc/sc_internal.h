@@ -78,8 +78,8 @@ hipError_t launch_reset(const FusedArgs& a, uint32_t n_state, hipStream_t stream
 hipError_t launch_fused(const FusedArgs& a, uint32_t tile_waves, uint32_t chunk_digis,
                         uint32_t stage, uint32_t grid, hipStream_t stream);
 hipError_t launch_cluster_dense(const uint8_t* adc_dense, const FusedArgs& a,
-                                uint32_t tile_waves, uint32_t chunk_digis, uint32_t grid,
-                                hipStream_t stream);
+                                uint32_t tile_waves, uint32_t chunk_digis, uint32_t stage,
+                                uint32_t grid, hipStream_t stream);
 hipError_t launch_unpack(const uint8_t* zs, const uint64_t* fed_off, uint32_t n_fed,
                          uint8_t* adc_dense, uint8_t* chan_status, EventResult* res,
                          hipStream_t stream);

@@ -1531,7 +1531,7 @@ int blocks_per_cu_for(bool dense) {
 constexpr int kRowDigis = 3 * kStripsPerChannel;
 
 // Tile shapes: W waves per tile, chunk_digis digis per tile (chunk_digis / W per wave) and the
-// stage size; the large stage exists for three shapes. stage 0 means the small one.
+// stage size; the large stage exists for four shapes. stage 0 means the small one.
 template <class F>
 bool dispatch(uint32_t w, uint32_t d, uint32_t stage, F&& f) {
     if (stage == 0u) stage = (uint32_t)kStageSmall;
@@ -1547,6 +1547,7 @@ bool dispatch(uint32_t w, uint32_t d, uint32_t stage, F&& f) {
     SC_CASE(2, 4096, kStageSmall)
     SC_CASE(4, 2048, kStageSmall) SC_CASE(4, 3072, kStageSmall) SC_CASE(4, 4096, kStageSmall)
     SC_CASE(2, 2048, kStageLarge) SC_CASE(2, 2880, kStageLarge) SC_CASE(4, 4096, kStageLarge)
+    SC_CASE(4, 6144, kStageLarge)
 #undef SC_CASE
     return false;
 }
@@ -1559,16 +1560,21 @@ bool tile_shape_supported(uint32_t waves, uint32_t d, uint32_t stage) {
 
 bool tile_shape_supports_modules(uint32_t waves, uint32_t d) {
     bool ok = false;
-    dispatch(waves, d, 0u, [&](auto, auto DW, auto) { ok = decltype(DW)::value >= kRowDigis; });
+    auto rows = [&](auto, auto DW, auto) { ok = decltype(DW)::value >= kRowDigis; };
+    if (!dispatch(waves, d, 0u, rows)) dispatch(waves, d, (uint32_t)kStageLarge, rows);
     return ok;
 }
 
 uint32_t stage_bytes_of(uint32_t stage) { return stage ? stage : (uint32_t)kStageSmall; }
 
+// The dense front end never reads the stage: it runs with the small one where the shape has it.
+uint32_t dense_stage(uint32_t waves, uint32_t d, uint32_t stage) {
+    return tile_shape_supported(waves, d, 0u) ? 0u : stage;
+}
+
 int fused_blocks_per_cu(uint32_t waves, uint32_t d, bool dense, bool modules, uint32_t stage) {
     int nb = 1;
-    // (the dense front end never reads the stage: it runs with the small one)
-    dispatch(waves, d, dense ? 0u : stage, [&](auto W, auto DW, auto SS) {
+    dispatch(waves, d, dense ? dense_stage(waves, d, stage) : stage, [&](auto W, auto DW, auto SS) {
         constexpr int w = decltype(W)::value, dw = decltype(DW)::value, st = decltype(SS)::value;
         if constexpr (dw >= kRowDigis) {
             nb = modules ? blocks_per_cu_for<w, dw, true, st>(dense)
@@ -1621,11 +1627,11 @@ hipError_t launch_fused(const FusedArgs& a, uint32_t waves, uint32_t d, uint32_t
 }
 
 hipError_t launch_cluster_dense(const uint8_t* dense, const FusedArgs& a, uint32_t waves,
-                                uint32_t d, uint32_t grid, hipStream_t stream) {
+                                uint32_t d, uint32_t stage, uint32_t grid, hipStream_t stream) {
     (void)hipGetLastError();
     const bool mod = a.cal.joins != nullptr;
     bool ok = false;
-    dispatch(waves, d, 0u, [&](auto W, auto DW, auto SS) {
+    dispatch(waves, d, dense_stage(waves, d, stage), [&](auto W, auto DW, auto SS) {
         constexpr int w = decltype(W)::value, dw = decltype(DW)::value, st = decltype(SS)::value;
         if constexpr (dw >= kRowDigis) {
             if (mod) hipLaunchKernelGGL((cluster_dense_kernel<w, dw, true, st>), dim3(grid), dim3(kWave * w), 0, stream, dense, a);

@@ -1170,7 +1170,7 @@ sc_status sc_cluster(sc_ctx* c, const uint8_t* adc_dense, sc_mem in_mem, sc_clus
     ws.clean = false;
     SC_HIP(c, hipEventRecord(c->ev0, c->stream));
     SC_HIP(c, launch_cluster_dense(d_in, a, c->tuning.tile_waves, c->tuning.chunk_digis,
-                                   grid_for(c, c->n_fed, true), c->stream));
+                                   c->tuning.stage_bytes, grid_for(c, c->n_fed, true), c->stream));
     SC_HIP(c, hipEventRecord(c->ev1, c->stream));
     SC_HIP(c, hipMemcpyAsync(ws.h_res.p, ws.res.p, sizeof(EventResult), hipMemcpyDeviceToHost, c->stream));
     SC_HIP(c, hipStreamSynchronize(c->stream));
@@ -1607,7 +1607,7 @@ sc_status sc_set_tuning(sc_ctx* c, const sc_tuning* t) {
         return fail(c, SC_ERR_INVALID_ARG,
                     "unsupported tuning (tile_waves 1, 2 or 4; chunk_digis 2048, 3072 or 4096, "
                     "1024 with one wave, 2880 with two; stage_bytes 0 or 6656, or 10240 with "
-                    "2 x 2048, 2 x 2880 or 4 x 4096)");
+                    "2 x 2048, 2 x 2880, 4 x 4096 or 4 x 6144)");
     if (c->modules && !tile_shape_supports_modules(t->tile_waves, t->chunk_digis))
         return fail(c, SC_ERR_INVALID_ARG,
                     "tile shape holds no module row (768 digis per wave) while modules are set");
@@ -1662,7 +1662,7 @@ sc_status sc_autotune(sc_ctx* c, const sc_event* ev, uint32_t n, sc_tuning* best
     std::vector<sc_tuning> cands;
     for (uint32_t st : {stage_bytes_of(0), 10240u})
         for (uint32_t w : {1u, 2u, 4u})
-            for (uint32_t d : {1024u, 2048u, 2880u, 3072u, 4096u})
+            for (uint32_t d : {1024u, 2048u, 2880u, 3072u, 4096u, 6144u})
                 for (uint32_t fm : {0u, 1u, 2u})
                     if (tile_shape_supported(w, d, st) &&
                         (!c->modules || tile_shape_supports_modules(w, d)))

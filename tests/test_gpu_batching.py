@@ -53,7 +53,7 @@ def test_full_detector_batch_exact(full, waves, chunk):
 LARGE_STAGE = 10240   # sc_tuning.stage_bytes of the large LDS stage (FEDs up to 10224 bytes)
 
 
-@pytest.mark.parametrize("waves,chunk", [(2, 2048), (2, 2880), (4, 4096)])
+@pytest.mark.parametrize("waves,chunk", [(2, 2048), (2, 2880), (4, 4096), (4, 6144)])
 def test_full_detector_batch_exact_large_stage(full, waves, chunk):
     cal, evs, refs, ctx = full
     before = ctx.tuning
@@ -275,7 +275,7 @@ def test_stress_distribution_and_overflow_batch():
         assert allcl["width"].max() >= 12
 
 
-@pytest.mark.parametrize("waves,chunk", [(2, 2048), (2, 2880), (4, 4096)])
+@pytest.mark.parametrize("waves,chunk", [(2, 2048), (2, 2880), (4, 4096), (4, 6144)])
 def test_stress_distribution_large_stage(waves, chunk):
     """The stress distribution's FEDs (about 8.2 KB) are past the small stage and inside the
     large one: staged and walked in LDS there, read from global memory with the small stage; the
@@ -334,7 +334,7 @@ def _edge_event(kind):
                                   "between_stages", "multichunk_fits_stage", "garbage"])
 @pytest.mark.parametrize("shape", [(1024, 1, 0), (3072, 1, 0), (2048, 2, 0), (2880, 2, 0),
                                    (4096, 2, 0), (2048, 4, 0), (2880, 2, LARGE_STAGE),
-                                   (4096, 4, LARGE_STAGE)])
+                                   (4096, 4, LARGE_STAGE), (6144, 4, LARGE_STAGE)])
 def test_edge_cases(kind, shape):
     zs, fo, noise, gain, bad = _edge_event(kind)
     ref = oracle.process_event(zs, fo, noise, gain, bad)
@@ -468,7 +468,7 @@ def test_autotune_identical_and_cached(full, tmp_path):
     with make_ctx(cal.noise, cal.gain, cal.bad, tune_cache=cache) as ctx:
         devs = [sc.Event(e.zs, e.fed_offset).to_device() for e in evs[:4]]
         best = ctx.autotune(devs)
-        assert best["chunk_digis"] in (1024, 2048, 2880, 3072, 4096) and best["tile_waves"] in (1, 2, 4)
+        assert best["chunk_digis"] in (1024, 2048, 2880, 3072, 4096, 6144) and best["tile_waves"] in (1, 2, 4)
         results, _, _, _ = run_fused(ctx, [(e.zs, e.fed_offset) for e in evs[:2]])
         for r, ref in zip(results, refs[:2]):
             compare_clusters(r[0], r[1], ref, "after autotune")

@@ -64,7 +64,7 @@ def test_full_detector_module_rows_exact(full, waves, chunk, order):
         ctx.tuning = before
 
 
-@pytest.mark.parametrize("waves,chunk", [(2, 2880), (4, 4096)])
+@pytest.mark.parametrize("waves,chunk", [(2, 2880), (4, 4096), (4, 6144)])
 def test_module_rows_with_the_large_stage(full, waves, chunk):
     cal, geo, evs, refs, ctx = full
     before = ctx.tuning
