@@ -338,7 +338,7 @@ __device__ WalkResult stage_and_walk(TileSmem<W, DW, S>& sm, const uint8_t* g, u
             // barrier: its wave issues ahead of the CU's other waves meanwhile
             __builtin_amdgcn_s_setprio(3);
             // lane k (mod 64) keeps channel k's payload position. Branch-free steps whose
-            // serial chain is only read, add, clamp. Record k ends where record k + 1's length
+            // serial chain is only read, add, clamp (vector instructions, uniform values). Record k ends where record k + 1's length
             // field starts, so the lengths and the fit test come from the positions afterwards:
             // a record fits the FED when its end is <= L, and since ends only grow, the records
             // that fit come first (past the first one that does not, the reads stay inside the
@@ -349,7 +349,11 @@ __device__ WalkResult stage_and_walk(TileSmem<W, DW, S>& sm, const uint8_t* g, u
             auto step = [&](uint32_t k, uint32_t& vpos) {
                 uint32_t o = pos + delta;
                 o = o < omax ? o : omax;
-                const uint32_t P = uni(lds_u16(sm.stage, o));
+                // the chain stays in vector registers (the empty asm keeps P there): the
+                // CU's one scalar unit, shared by its four SIMDs, is busy with the other
+                // waves' scalar work, and a scalar chain would wait for it at every step
+                uint32_t P = lds_u16(sm.stage, o);
+                asm volatile("" : "+v"(P));
                 vpos = __builtin_amdgcn_inverse_ballot_w64(1ull << (k & 63u)) ? pos + 2u : vpos;
                 pos += 2u + P;
             };
