@@ -507,12 +507,16 @@ __device__ uint32_t plan_chunks(TileSmem<W, DW, S>& sm, uint32_t w, uint32_t c_l
 
 // Expand the records of channels [c0, c1) into the digi list dl.
 // From the staged FED (LDS) in two passes: one lane per channel writes, at the first digi slot
-// of each of its records, a marker (bit 31 | source offset of the ADC bytes << 15 | channel << 8
-// | first strip); then one lane per digi finds the record it belongs to (the last marker at or
-// before it: a ballot of the marker bits, carried across steps) and writes its digi word. The
-// list's other slots never carry bit 31: the digi words use bits 0-27, and the kernel clears
-// the list before its first tile. From global memory (a FED larger than the stage): one lane
-// per channel expands its runs, four ADC bytes per iteration.
+// o of each of its records, a marker (bit 31 | (source offset of the ADC bytes - o) << 15 |
+// channel << 8 | (first strip - o) mod 256); then one lane per digi, at slot j, takes the last
+// marker at or before it and writes its digi word: ADC byte at (its source field) + j, strip
+// (its low byte + j) mod 256. Records take their slots in the order of their bytes in the FED,
+// and between two records the source offset grows by at least the first one's digis plus the
+// next one's 2-byte header, so the source field grows with every marker and the last marker at
+// or before a slot is the largest: a running maximum over the lanes, carried across steps. The
+// list's other slots never carry bit 31 (the digi words use bits 0-27, and the kernel clears the
+// list before its first tile), and slot 0 holds a marker. From global memory (a FED larger than
+// the stage): one lane per channel expands its runs, four ADC bytes per iteration.
 template <bool kStaged, class P, int W, int DW, int S>
 __device__ __forceinline__ void build_zs(TileSmem<W, DW, S>& sm, uint32_t w, uint32_t* dl, P src,
                                          uint32_t c0, uint32_t c1) {
@@ -528,7 +532,8 @@ __device__ __forceinline__ void build_zs(TileSmem<W, DW, S>& sm, uint32_t w, uin
             uint32_t q = 0;
             while (q < len) {
                 const uint32_t first = src[p + q], cnt = src[p + q + 1];
-                dl[o] = 0x80000000u | ((p + q + 2) << 15) | (ch << 8) | first;
+                // every digi before slot o has its ADC byte before p + q + 2: no underflow
+                dl[o] = 0x80000000u | ((p + q + 2 - o) << 15) | (ch << 8) | ((first - o) & 0xffu);
                 o += cnt;
                 q += 2 + cnt;
             }
@@ -536,23 +541,23 @@ __device__ __forceinline__ void build_zs(TileSmem<W, DW, S>& sm, uint32_t w, uin
         __builtin_amdgcn_s_setprio(0);
         wave_sync();
         const uint32_t n = uni(sm.ch_base[c1 + w] - b0);
-        const uint64_t upto = lane() == kWave - 1 ? ~0ull : (2ull << lane()) - 1ull;
-        uint32_t carry_m = 0u, carry_j = 0u;   // the last marker seen and its slot (uniform)
-        for (uint32_t j0 = 0; j0 < n; j0 += kWave) {
-            const uint32_t j = j0 + lane();
-            const uint32_t v = j < n ? dl[j] : 0u;
-            const uint64_t heads = __ballot((v >> 31) != 0u);
-            const uint64_t mine = heads & upto;
-            const uint32_t hl = mine ? 63u - (uint32_t)__clzll((long long)mine) : 0u;
-            const uint32_t hv = __shfl(v, (int)hl);
-            const uint32_t m = mine ? hv : carry_m;
-            const uint32_t k = j - (mine ? j0 + hl : carry_j);
-            const uint32_t so = (m >> 15) & 0xffffu, first = m & 0xffu, ch = (m >> 8) & 0x7fu;
-            if (j < n) dl[j] = (ch << 16) | ((first + k) << 8) | src[so + k];
-            if (heads) {
-                const uint32_t last = 63u - (uint32_t)__clzll((long long)heads);
-                carry_m = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)last);
-                carry_j = j0 + last;
+        // two steps of 64 slots per iteration, both loads first (each lane reads and writes
+        // only its own slots); a slot at or past n reads slot 0 and is neither used nor written
+        uint32_t carry = 0u;   // the last marker of the steps before (uniform)
+        for (uint32_t j0 = 0; j0 < n; j0 += 2u * kWave) {
+            const uint32_t ja = j0 + lane(), jb = ja + kWave;
+            const uint32_t va = dl[ja < n ? ja : 0u], vb = dl[jb < n ? jb : 0u];
+            const uint32_t ma = __builtin_elementwise_max(wave_incl_max(ja < n ? va : 0u), carry);
+            const uint32_t mb = __builtin_elementwise_max(wave_incl_max(jb < n ? vb : 0u),
+                                                          last_lane(ma));
+            carry = last_lane(mb);
+            if (ja < n) {
+                const uint32_t so = ((ma >> 15) & 0xffffu) + ja, ch = (ma >> 8) & 0x7fu;
+                dl[ja] = (ch << 16) | (((ma + ja) & 0xffu) << 8) | src[so];
+            }
+            if (jb < n) {
+                const uint32_t so = ((mb >> 15) & 0xffffu) + jb, ch = (mb >> 8) & 0x7fu;
+                dl[jb] = (ch << 16) | (((mb + jb) & 0xffu) << 8) | src[so];
             }
         }
     } else {
