@@ -321,6 +321,22 @@ def _edge_event(kind):
         # 20 full channels: 5 KB of ZS (fits the stage) but 5120 digis
         runs = {192 + c: [(0, [4] + [3] * 254), (255, [3])] for c in range(20)}
         zs, fo = event_from_runs(runs, n_fed)
+    elif kind == "group_heads":
+        # the first channel of every channel group (W = 1, 2, 4) malformed (a run of count 0)
+        # and the next one empty, so that a group's first digi slot belongs to a later channel;
+        # channels of 40 one-strip runs (three bytes a digi); in the first group 1,576 digis
+        # (more than one chunk at up to 1,536 digis a wave) with an empty channel among the full
+        # ones
+        full = [(0, [4] + [3] * 254), (255, [3])]
+        alt = [(2 * k, [5]) for k in range(40)]
+        runs = {}
+        for g in (0, 24, 48, 72):
+            runs[g] = [(10, [])]
+            runs[g + 2] = alt
+        for c in (3, 4, 6, 7, 8, 9):
+            runs[c] = full
+        runs[60] = [(0, [4, 3]), (2, [3, 4])]   # adjacent runs: one cluster
+        zs, fo = event_from_runs(runs, n_fed)
     elif kind == "garbage":
         rng = np.random.default_rng(7)
         zs = rng.integers(0, 256, size=30000, dtype=np.uint8)
@@ -331,7 +347,8 @@ def _edge_event(kind):
 
 
 @pytest.mark.parametrize("kind", ["all_empty", "zero_length_feds", "full_fed", "alternating_fed",
-                                  "between_stages", "multichunk_fits_stage", "garbage"])
+                                  "between_stages", "multichunk_fits_stage", "group_heads",
+                                  "garbage"])
 @pytest.mark.parametrize("shape", [(1024, 1, 0), (3072, 1, 0), (2048, 2, 0), (2880, 2, 0),
                                    (4096, 2, 0), (2048, 4, 0), (2880, 2, LARGE_STAGE),
                                    (4096, 4, LARGE_STAGE), (6144, 4, LARGE_STAGE)])
