@@ -580,7 +580,7 @@ sc_status run_batch(sc_ctx* c, const sc_event* ev, uint32_t n, sc_clusters* out,
 }
 
 // ---- autotuner cache (tiny JSON: {"<device>/<n_fed>": [chunk, tile waves, tiles/CU,
-//      fed_major, graph]}) ----
+//      fed_major, graph, stage bytes]}) ----
 std::string tune_key(const sc_ctx* c) {
     return c->device_name + "/" + std::to_string(c->n_fed);
 }
