@@ -1050,10 +1050,16 @@ __device__ __forceinline__ void write_pass(const TileSmem<W, DW, S>& sm, const u
         const bool endA = memA && !contB;
         const bool endB = memB && !next_contA;
         const bool eB = endB && l != 63u;
-        // (every lane forms both: the divisions run for the whole wavefront in any case)
+        // rec1: the record of A's cluster where it ends here, else of B's (the division runs for
+        // the whole wavefront in any case). rec2 serves B where A's cluster ended at A: B then
+        // does not continue it and heads its own run, so where it is stored (B's cluster ends
+        // here, or lane 63 keeps it open as it stands) it is a one-strip record: first = its
+        // strip, width 1, barycenter strip + 1/2 exactly (the quotient (2 s c + c) / (2 c), and
+        // the midpoint when c = 0), in a module row too (its channel is its own)
         const u32x4 rec1 = make_record<kMod>(fed, endA ? dA : dB, endA ? rpA : rpB,
                                              endA ? CA : CB, endA ? MA : MB, endA ? MhA : MhB);
-        const u32x4 rec2 = make_record<kMod>(fed, dB, rpB, CB, MB, MhB);
+        const u32x4 rec2 = u32x4{fed * kNch + d_ch(dB), d_strip(dB) | (1u << 16), CB,
+                                 __float_as_uint((float)d_strip(dB) + 0.5f)};
         const u32x4 recB = endA ? rec2 : rec1;
         const uint64_t ebA = __ballot(endA), ebB = __ballot(eB);
         const uint32_t prec = count_below(ebB, count_below(ebA, rc));
