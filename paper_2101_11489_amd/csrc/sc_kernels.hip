@@ -818,8 +818,19 @@ __device__ __forceinline__ void form_step(uint32_t* dl, uint32_t base, uint32_t 
     const bool next_contA = from_next_lane(contA ? 1u : 0u) != 0u;
     const bool endA = actA && !contB;
     const bool endB = actB && !next_contA;
-    const uint32_t markA = cluster_mark<kMod>(endA, rpA, QA, SA, cal.t_cluster);
-    const uint32_t markB = cluster_mark<kMod>(endB, rpB, QB, SB, cal.t_cluster);
+    // Where A's run ends at A, B does not continue it, so B's run, where it ends here (or as it
+    // stands at lane 63), is B alone. The threshold of a one-strip run needs no sum: the square
+    // root of the rounded square of a float is that float (radix 2, round to nearest, the square
+    // neither underflowing nor overflowing), so it is (float)a >= t * n exactly; outside that
+    // range it is left to settle_runs. The tree-sum test then serves A's run, else B's.
+    const uint32_t mark1 = cluster_mark<kMod>(endA || endB, endA ? rpA : rpB, endA ? QA : QB,
+                                              endA ? SA : SB, cal.t_cluster);
+    const bool n_ok = nB >= 0x1p-60f && nB <= 0x1p60f;
+    const uint32_t single = !(endB && sdB) ? 0u
+                            : !n_ok ? kRedoBit
+                            : afB >= cal.t_cluster * nB ? kAccBit : 0u;
+    const uint32_t markA = endA ? mark1 : 0u;
+    const uint32_t markB = endA ? single : mark1;
     const bool eB = markB != 0u && l != 63u;
     // (LDS atomic ORs: no read back; each run has one end, so the words differ)
     if (markA) __hip_atomic_fetch_or(&dl[jA - rpA], markA, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
