@@ -113,6 +113,42 @@ def test_runs_at_the_cluster_threshold(waves, chunk):
             assert bary_bit_exact(res[0], ref)
 
 
+@pytest.mark.parametrize("waves,chunk", [(1, 1024), (2, 2880), (4, 2048)])
+def test_one_strip_runs_at_the_cluster_threshold(waves, chunk):
+    # isolated strips, so that both digis of every lane end a run: digi A's run takes the
+    # tree-sum test, digi B's the one-strip test. Noise at fl(a / t) and up to three binary32
+    # steps beside it, and tiny (below 2^-60 the one-strip test leaves the run to the
+    # sequential sum)
+    thr = dict(t_seed=0.3, t_channel=0.25, t_cluster=5.0)
+    rng = np.random.default_rng(11489)
+    noise, gain, bad = calib_arrays(1)
+    tiny = [0.0, 1e-40, 1e-30, 2.0 ** -70, 2.0 ** -63, 2.0 ** -61, 2.0 ** -60, 2.0 ** -59]
+    chan_runs = {}
+    for ch in range(16):   # 6.3 KB of ZS: the FED fits the LDS stage
+        recs = []
+        for s in range(ch % 2, 256, 2):
+            a = int(rng.integers(1, 256))
+            k = int(rng.integers(0, 9))
+            if k < 7:
+                n = np.float32(a) / np.float32(thr["t_cluster"])
+                for _ in range(abs(k - 3)):
+                    n = np.nextafter(n, np.float32(np.inf if k > 3 else 0.0), dtype=np.float32)
+            else:
+                n = np.float32(tiny[int(rng.integers(0, len(tiny)))])
+            noise[ch * 256 + s] = n
+            recs.append((s, [a]))
+        chan_runs[ch] = recs
+    zs, fo = event_from_runs(chan_runs)
+    ref = oracle.process_event(zs, fo, noise, gain, bad, **thr)
+    assert 0 < ref.cl.size < 16 * 128   # some runs pass the threshold and some do not
+    with make_ctx(noise, gain, bad, **thr) as ctx:
+        ctx.tuning = {"chunk_digis": chunk, "tile_waves": waves, "use_graph": 0}
+        (res,), rc, _, _ = run_fused(ctx, [(zs, fo)])
+        assert rc == sc.SC_OK
+        compare_clusters(res[0], res[1], ref, "one-strip runs")
+        assert bary_bit_exact(res[0], ref)
+
+
 def test_generated_config0_batch(cfg0):
     cfg, cal, evs, ctx = cfg0
     refs = [oracle.process_event(e.zs, e.fed_offset, cal.noise, cal.gain, cal.bad) for e in evs]
